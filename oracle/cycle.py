@@ -1,0 +1,169 @@
+"""The oracle's PIC cycle (FP64, plain NumPy).
+
+Per step n (fields E^n, B^n live at integer times in real space, momenta at
+half-integer times):
+  1. gather E^n, B^n at x^n, Boris push u^{n-1/2} -> u^{n+1/2},
+     move x^{n+1} = x^n + dt v^{n+1/2};
+  2. deposit rho^n at x^n, J^{n+1/2} at x^{n+1/2} = (x^n + x^{n+1})/2 with
+     v^{n+1/2}, rho^{n+1} at x^{n+1} (the time levels the paper's Eq. (1a)
+     uses), immobile species included in both densities;
+  3. forward transforms (FFT along z, discrete Hankel along r) of E, B, J,
+     rho^n, rho^{n+1};
+  4. spectral current correction, then the order-p PSATD update;
+  5. inverse transforms to real space;
+  6. moving window (when enabled): zmin advances by dz, fields shift one cell
+     toward the tail (the head column is zeroed), particles behind the new
+     zmin are removed and a fresh lattice column is injected at the head.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List
+
+import numpy as np
+
+from . import spectral as sp
+from . import particles as pt
+
+
+@dataclasses.dataclass
+class OSpecies:
+    name: str
+    q: float
+    m: float
+    mobile: bool
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    ux: np.ndarray
+    uy: np.ndarray
+    uz: np.ndarray
+    w: np.ndarray
+    inject: bool
+    ppc: tuple
+    density: float
+    diag: bool
+
+
+class OracleSim:
+    def __init__(self, wl, current_correction: bool = True):
+        self.nz, self.nr, self.M = wl.nz, wl.nr, wl.n_modes
+        self.dz, self.dr, self.dt = wl.dz, wl.dr, wl.dt
+        self.zmin0 = wl.zmin
+        self.zmin = wl.zmin
+        self.order = wl.order
+        self.moving_window = wl.moving_window
+        self.correct = current_correction
+        self.n_shift = 0
+        self.hankel = [sp.HankelPair(m, wl.nr, wl.dr, wl.kperp_grid) for m in range(self.M)]
+        self.kzm = sp.kz_modified(sp.kz_grid(wl.nz, wl.dz), wl.dz, wl.order)[None, :]
+        shape = (self.M, 3, self.nr, self.nz)
+        self.E = np.zeros(shape, dtype=np.complex128)
+        self.B = np.zeros(shape, dtype=np.complex128)
+        self.species: List[OSpecies] = []
+        for s in wl.species:
+            self.species.append(OSpecies(
+                s.name, s.q, s.m, s.mobile,
+                s.x.astype(np.float64).copy(), s.y.astype(np.float64).copy(),
+                s.z.astype(np.float64).copy(),
+                s.ux.astype(np.float64), s.uy.astype(np.float64), s.uz.astype(np.float64),
+                s.w.astype(np.float64), s.inject, tuple(s.ppc), s.density, s.diag))
+        # last step's intermediates (exposed for stage-by-stage parity tests)
+        self.J = None
+        self.rho_old = None
+        self.rho_new = None
+
+    # -- helpers -----------------------------------------------------------
+    def grid(self):
+        return {"nz": self.nz, "nr": self.nr, "dz": self.dz, "dr": self.dr, "zmin": self.zmin}
+
+    # -- stage 1: gather + push -------------------------------------------
+    def gather_push(self):
+        g = self.grid()
+        for s in self.species:
+            if not s.mobile:
+                s.xn = (s.x, s.y, s.z)
+                continue
+            s.xn = (s.x.copy(), s.y.copy(), s.z.copy())
+            Ex, Ey, Ez = pt.gather_cartesian(self.E, s.x, s.y, s.z, g)
+            Bx, By, Bz = pt.gather_cartesian(self.B, s.x, s.y, s.z, g)
+            s.ux, s.uy, s.uz = pt.boris(s.ux, s.uy, s.uz, Ex, Ey, Ez, Bx, By, Bz,
+                                        s.q, s.m, self.dt)
+            ginv = 1.0 / np.sqrt(1.0 + s.ux ** 2 + s.uy ** 2 + s.uz ** 2)
+            s.vx, s.vy, s.vz = s.ux * ginv, s.uy * ginv, s.uz * ginv
+            s.x = s.x + self.dt * s.vx
+            s.y = s.y + self.dt * s.vy
+            s.z = s.z + self.dt * s.vz
+
+    # -- stage 2: deposit -------------------------------------------------
+    def deposit(self):
+        g = self.grid()
+        M = self.M
+        rho_old = np.zeros((M, self.nr, self.nz), np.complex128)
+        rho_new = np.zeros_like(rho_old)
+        J = np.zeros((M, 3, self.nr, self.nz), np.complex128)
+        for s in self.species:
+            qw = s.q * s.w
+            xo, yo, zo = s.xn
+            rho_old += pt.deposit_rho(M, qw, xo, yo, zo, g)
+            rho_new += pt.deposit_rho(M, qw, s.x, s.y, s.z, g)
+            if s.mobile:
+                xh, yh, zh = 0.5 * (xo + s.x), 0.5 * (yo + s.y), 0.5 * (zo + s.z)
+                J += pt.deposit_current(M, qw, xh, yh, zh, s.vx, s.vy, s.vz, g)
+        self.J, self.rho_old, self.rho_new = J, rho_old, rho_new
+
+    # -- stage 3-5: spectral push -----------------------------------------
+    def spectral_push(self):
+        for m in range(self.M):
+            hk = self.hankel[m]
+            kp = hk.k[:, None]
+            nus = sp.hankel_orders(m)
+            Eh = tuple(hk.forward(self.E[m, c], nus[c]) for c in range(3))
+            Bh = tuple(hk.forward(self.B[m, c], nus[c]) for c in range(3))
+            Jh = tuple(hk.forward(self.J[m, c], nus[c]) for c in range(3))
+            r0 = hk.forward(self.rho_old[m], m)
+            r1 = hk.forward(self.rho_new[m], m)
+            if self.correct:
+                Jh = sp.current_correction(Jh, r0, r1, self.dt, kp, self.kzm)
+            En, Bn = sp.psatd_push(Eh, Bh, Jh, r0, r1, self.dt, kp, self.kzm)
+            for c in range(3):
+                self.E[m, c] = hk.backward(En[c], nus[c])
+                self.B[m, c] = hk.backward(Bn[c], nus[c])
+        if self.moving_window:
+            self.move_window()
+
+    # -- stage 6: moving window -------------------------------------------
+    def move_window(self):
+        self.n_shift += 1
+        self.zmin = self.zmin0 + self.n_shift * self.dz
+        for F in (self.E, self.B):
+            F[..., :-1] = F[..., 1:].copy()
+            F[..., -1] = 0.0
+        for s in self.species:
+            keep = s.z >= self.zmin
+            for a in ("x", "y", "z", "ux", "uy", "uz", "w"):
+                setattr(s, a, getattr(s, a)[keep])
+            if s.inject:
+                x, y, z, w = pt.lattice_column(self.nz - 1, self.zmin, self.nr, self.dz,
+                                               self.dr, s.ppc, s.density)
+                s.x = np.concatenate([s.x, x])
+                s.y = np.concatenate([s.y, y])
+                s.z = np.concatenate([s.z, z])
+                s.w = np.concatenate([s.w, w.astype(np.float64)])
+                zero = np.zeros(x.shape[0])
+                s.ux = np.concatenate([s.ux, zero])
+                s.uy = np.concatenate([s.uy, zero])
+                s.uz = np.concatenate([s.uz, zero])
+
+    def step(self, n: int = 1):
+        for _ in range(n):
+            self.gather_push()
+            self.deposit()
+            self.spectral_push()
+
+    # -- diagnostics helpers ----------------------------------------------
+    def species_by_name(self, name):
+        for s in self.species:
+            if s.name == name:
+                return s
+        raise KeyError(name)

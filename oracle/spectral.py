@@ -1,0 +1,183 @@
+"""Spectral side of the oracle (FP64): grids, finite-order wavenumber, Hankel
+transform pair, quasi-cylindrical spectral operators, current correction and
+the PSATD update.
+
+Conventions (the paper's operator table fixes them, see the notes below):
+  * a field is F(r, theta, z) = sum_{m=-M..M} F_m(r, z) exp(-i m theta) with
+    F_{-m} = conj(F_m) for real fields;
+  * vector fields are carried as F_+ = (F_r - i F_theta)/2,
+    F_- = (F_r + i F_theta)/2 and F_z; in mode m the Hankel order of F_+ is
+    m + 1, of F_- is m - 1 and of F_z (and of scalars) is m;
+  * plasma units, c = 1: the paper's Eqs. (1a)-(1b) are written with the
+    vacuum permittivity set to one and B standing for cB, which is exactly the
+    form they take in these units.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+from math import factorial
+
+import numpy as np
+from scipy.special import jv, jn_zeros
+
+KPERP_J0_ZEROS, KPERP_SINE, KPERP_JM_ZEROS = 0, 1, 2
+
+
+# ---------------------------------------------------------------------------
+# Finite-order modification (paper, Sec. "Finite order pseudo-spectral
+# solvers", Eq. (3) and Eq. (5))
+# ---------------------------------------------------------------------------
+def fornberg_alpha_exact(n: int):
+    """Centered stencil coefficients alpha_{n,j}, j = 1..n, of the order-2n
+    first derivative, Eq. (3): (-1)^(j+1) 2 (n!)^2 / ((n-j)! (n+j)!), exact."""
+    return [Fraction((-1) ** (j + 1) * 2 * factorial(n) ** 2,
+                     factorial(n - j) * factorial(n + j)) for j in range(1, n + 1)]
+
+
+def fornberg_alpha(n: int) -> np.ndarray:
+    return np.array([float(a) for a in fornberg_alpha_exact(n)], dtype=np.float64)
+
+
+def kz_grid(nz: int, dz: float) -> np.ndarray:
+    """Discrete longitudinal wavenumbers of a periodic z grid (FFT order,
+    Nyquist at -pi/dz)."""
+    return 2.0 * np.pi * np.fft.fftfreq(nz, dz)
+
+
+def kz_modified(kz: np.ndarray, dz: float, order: int) -> np.ndarray:
+    """Modified wavenumber [k_z] = sum_j alpha_{n,j} sin(k_z j dz)/(j dz),
+    Eq. (5), with stencil order p = 2n.  order == 0 stands for the infinite
+    order (unmodified k_z)."""
+    kz = np.asarray(kz, dtype=np.float64)
+    if order == 0:
+        return kz.copy()
+    if order < 2 or order % 2:
+        raise ValueError("stencil order must be even and >= 2 (or 0 for infinite)")
+    n = order // 2
+    alpha = fornberg_alpha(n)
+    out = np.zeros_like(kz)
+    for j in range(1, n + 1):
+        out += alpha[j - 1] * np.sin(kz * j * dz) / (j * dz)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Radial grid and discrete Hankel transform pair (the paper names a Hankel
+# transform along r for the quasi-cylindrical scheme; the discrete pair is
+# this implementation's reading, see the design notes)
+# ---------------------------------------------------------------------------
+def r_grid(nr: int, dr: float) -> np.ndarray:
+    """Cell-centred radial nodes r_i = (i + 1/2) dr."""
+    return (np.arange(nr, dtype=np.float64) + 0.5) * dr
+
+
+def kperp_grid(m: int, nr: int, dr: float, kind: int = KPERP_J0_ZEROS) -> np.ndarray:
+    """Radial wavenumbers of mode m (all strictly positive).
+
+    KPERP_J0_ZEROS (default): k_i = j_{0,i}/R for every mode.  On this grid
+      the synthesis bases of orders 0, 1 and 2 all interpolate smooth data
+      accurately, so the spectral operators reproduce real-space derivatives,
+      and the matrices stay well conditioned (< 2e4 at Nr = 256).
+    KPERP_SINE: k_i = (i + 1) pi / R (well conditioned but a poor interpolant
+      for orders 0 and 1; kept for comparison).
+    KPERP_JM_ZEROS: k_i = j_{m,i}/R (the order-0 basis of mode 1 is then
+      nearly singular)."""
+    R = nr * dr
+    if kind == KPERP_SINE:
+        return (np.arange(nr, dtype=np.float64) + 1.0) * np.pi / R
+    if kind == KPERP_JM_ZEROS:
+        return jn_zeros(m, nr) / R
+    if kind == KPERP_J0_ZEROS:
+        return jn_zeros(0, nr) / R
+    raise ValueError(kind)
+
+
+def bessel_synthesis(nu: int, r: np.ndarray, k: np.ndarray) -> np.ndarray:
+    """Backward (synthesis) matrix B_nu[i_r, i_k] = J_nu(k_ik r_ir)."""
+    return jv(nu, np.outer(r, k))
+
+
+class HankelPair:
+    """Forward F_nu = inverse(B_nu) and backward B_nu matrices of one mode for
+    the three orders nu = m - 1, m, m + 1 used by F_-, scalars/F_z and F_+."""
+
+    def __init__(self, m: int, nr: int, dr: float, kind: int = KPERP_J0_ZEROS):
+        self.m = m
+        self.r = r_grid(nr, dr)
+        self.k = kperp_grid(m, nr, dr, kind)
+        self.B = {}
+        self.F = {}
+        for nu in (m - 1, m, m + 1):
+            B = bessel_synthesis(nu, self.r, self.k)
+            self.B[nu] = B
+            self.F[nu] = np.linalg.inv(B)
+
+    def forward(self, g: np.ndarray, nu: int) -> np.ndarray:
+        """Real space [r, z] -> spectral [k_perp, k_z]: FFT along z, then F_nu."""
+        return self.F[nu] @ np.fft.fft(g, axis=-1)
+
+    def backward(self, gh: np.ndarray, nu: int) -> np.ndarray:
+        """Spectral [k_perp, k_z] -> real space [r, z]: B_nu, then inverse FFT."""
+        return np.fft.ifft(self.B[nu] @ gh, axis=-1)
+
+
+# ---------------------------------------------------------------------------
+# Quasi-cylindrical spectral operators (paper, Eqs. (2a)-(2b)); kp broadcasts
+# along k_perp (shape [Nr, 1]), kzm is [k_z] (shape [1, Nz]).
+# ---------------------------------------------------------------------------
+def grad(s, kp, kzm):
+    """Spectral gradient of a scalar, Eq. (2a): (-kp s/2, +kp s/2, i[k_z] s)."""
+    return (-kp * s / 2.0, kp * s / 2.0, 1j * kzm * s)
+
+
+def curl(v, kp, kzm):
+    """Spectral curl of a vector (V_+, V_-, V_z), Eq. (2b)."""
+    vp, vm, vz = v
+    return (kzm * vp - 1j * kp * vz / 2.0,
+            -kzm * vm - 1j * kp * vz / 2.0,
+            1j * kp * (vp + vm))
+
+
+def div(v, kp, kzm):
+    """Spectral divergence consistent with Eqs. (2a)-(2b):
+    kp (V_+ - V_-) + i[k_z] V_z, so that div(grad s) = -(kp^2 + [k_z]^2) s."""
+    vp, vm, vz = v
+    return kp * (vp - vm) + 1j * kzm * vz
+
+
+def current_correction(J, rho_old, rho_new, dt, kp, kzm):
+    """Spectral current correction: J <- J + grad F with
+    F = (div J + (rho_new - rho_old)/dt) / k^2, so that afterwards
+    div J = -(rho_new - rho_old)/dt exactly (the paper requires charge
+    conservation, Sec. "Finite order pseudo-spectral solvers"; this is its
+    global spectral form on one domain)."""
+    k2 = kp ** 2 + kzm ** 2
+    F = (div(J, kp, kzm) + (rho_new - rho_old) / dt) / k2
+    g = grad(F, kp, kzm)
+    return tuple(J[c] + g[c] for c in range(3))
+
+
+def psatd_push(E, B, J, rho_old, rho_new, dt, kp, kzm):
+    """One PSATD step, Eqs. (1a)-(1b) with the operators of Eqs. (2a)-(2b)
+    and k_z replaced by [k_z] everywhere, including inside k, C and S.
+
+    E^{n+1} = C E + (S/k) curl B - (S/k) J
+              + (1/k^2) grad[(S/(k dt) - 1) rho_new + (C - S/(k dt)) rho_old]
+    B^{n+1} = C B - (S/k) curl E + ((1 - C)/k^2) curl J
+    """
+    k = np.sqrt(kp ** 2 + kzm ** 2)
+    C = np.cos(k * dt)
+    S = np.sin(k * dt)
+    x = k * dt
+    cB = curl(B, kp, kzm)
+    cE = curl(E, kp, kzm)
+    cJ = curl(J, kp, kzm)
+    g = grad((S / x - 1.0) * rho_new + (C - S / x) * rho_old, kp, kzm)
+    En = tuple(C * E[c] + (S / k) * cB[c] - (S / k) * J[c] + g[c] / k ** 2 for c in range(3))
+    Bn = tuple(C * B[c] - (S / k) * cE[c] + ((1.0 - C) / k ** 2) * cJ[c] for c in range(3))
+    return En, Bn
+
+
+def hankel_orders(m: int):
+    """Hankel orders of the (+, -, z) components of mode m."""
+    return (m + 1, m - 1, m)

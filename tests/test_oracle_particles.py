@@ -1,0 +1,168 @@
+"""Pins of the oracle's particle side: deposit, gather, Boris push."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import particles as pt
+from workloads import charge_to_weight, plasma_scales, random_particles
+
+GRID = {"nz": 24, "nr": 12, "dz": 0.1, "dr": 0.15, "zmin": 0.3}
+
+
+def _vol():
+    return pt.ring_volume(GRID["nr"], GRID["dr"], GRID["dz"])
+
+
+def test_charge_partition_of_unity():
+    p = random_particles(500, GRID["nz"], GRID["nr"] - 1, GRID["dz"], GRID["dr"],
+                         GRID["zmin"], seed=1)
+    qw = -p["w"].astype(np.float64)
+    rho = pt.deposit_rho(2, qw, p["x"], p["y"], p["z"], GRID)
+    total = (rho[0] * _vol()[:, None]).sum()
+    assert total.real == pytest.approx(qw.sum(), rel=1e-13)
+    assert abs(total.imag) < 1e-12
+
+
+def test_single_particle_mode_phase():
+    # away from the axis every node of mode 1 carries exp(i theta_p) times mode 0
+    th = 0.77
+    r = 0.9
+    x, y, z = np.array([r * np.cos(th)]), np.array([r * np.sin(th)]), np.array([1.234])
+    rho = pt.deposit_rho(3, np.array([2.0]), x, y, z, GRID)
+    nz_ = rho[0] != 0
+    assert nz_.sum() == 4
+    np.testing.assert_allclose(rho[1][nz_] / rho[0][nz_], np.exp(1j * th), rtol=1e-13)
+    np.testing.assert_allclose(rho[2][nz_] / rho[0][nz_], np.exp(2j * th), rtol=1e-13)
+
+
+def test_ring_current_phases():
+    # a ring of particles (uniform in theta) sharing one Cartesian velocity v:
+    # mode 0 of J_z is rho_0 v_z; J_x + i J_y = 2 J_{-,1} = rho_0 (v_x + i v_y);
+    # mode-0 J_+/J_- and mode-1 J_+ cancel around the ring
+    L = 8
+    th = 2 * np.pi * np.arange(L) / L + 0.1
+    r, z = 0.8, 1.0
+    x, y, zz = r * np.cos(th), r * np.sin(th), np.full(L, z)
+    qw = np.full(L, 0.5)
+    v = (0.3, -0.2, 0.9)
+    rho = pt.deposit_rho(2, qw, x, y, zz, GRID)
+    J = pt.deposit_current(2, qw, x, y, zz, np.full(L, v[0]), np.full(L, v[1]),
+                           np.full(L, v[2]), GRID)
+    np.testing.assert_allclose(J[0, 2], rho[0] * v[2], atol=1e-13)
+    np.testing.assert_allclose(2 * J[1, 1], rho[0] * (v[0] + 1j * v[1]), atol=1e-13)
+    for a in (J[0, 0], J[0, 1], J[1, 0], rho[1]):
+        assert np.abs(a).max() < 1e-13
+
+
+def _gather(Fm, x, y, z):
+    return pt.gather_cartesian(Fm, x, y, z, GRID)
+
+
+def test_gather_uniform_cartesian_field_everywhere():
+    # a uniform Cartesian field E0 is E_{z,0} = E0_z and E_{-,1} = (E0_x + i E0_y)/2
+    # (Hankel order 0, smooth through the axis): linear interpolation must
+    # return E0 exactly at every particle, including next to the axis
+    E0 = (0.3, -1.2, 0.7)
+    Fm = np.zeros((2, 3, GRID["nr"], GRID["nz"]), complex)
+    Fm[0, 2] = E0[2]
+    Fm[1, 1] = (E0[0] + 1j * E0[1]) / 2
+    p = random_particles(300, GRID["nz"], GRID["nr"] - 1, GRID["dz"], GRID["dr"],
+                         GRID["zmin"], seed=2)
+    ex, ey, ez = _gather(Fm, p["x"], p["y"], p["z"])
+    np.testing.assert_allclose(ex, E0[0], atol=1e-13)
+    np.testing.assert_allclose(ey, E0[1], atol=1e-13)
+    np.testing.assert_allclose(ez, E0[2], atol=1e-13)
+
+
+def test_gather_radial_linear_field_through_axis():
+    # E_r = a r (mode 0: E_+ = E_- = a r / 2, Hankel orders +-1, odd through
+    # the axis): the ghost-node parity makes linear interpolation exact down
+    # to r = 0, giving E_x + i E_y = a (x + i y)
+    a = 1.7
+    r = (np.arange(GRID["nr"]) + 0.5) * GRID["dr"]
+    Fm = np.zeros((1, 3, GRID["nr"], GRID["nz"]), complex)
+    Fm[0, 0] = Fm[0, 1] = (a * r / 2)[:, None]
+    p = random_particles(300, GRID["nz"], GRID["nr"] - 1, GRID["dz"], GRID["dr"],
+                         GRID["zmin"], seed=3)
+    ex, ey, ez = _gather(Fm, p["x"], p["y"], p["z"])
+    np.testing.assert_allclose(ex, a * p["x"], atol=1e-13)
+    np.testing.assert_allclose(ey, a * p["y"], atol=1e-13)
+
+
+def test_gather_linear_in_z_and_r():
+    # F_z = c0 + c1 z_rel + c2 r in mode 0: exact away from the axis and the
+    # periodic seam
+    c0, c1, c2 = 0.2, -0.7, 1.3
+    r = (np.arange(GRID["nr"]) + 0.5) * GRID["dr"]
+    zrel = np.arange(GRID["nz"]) * GRID["dz"]
+    Fm = np.zeros((1, 3, GRID["nr"], GRID["nz"]), complex)
+    Fm[0, 2] = c0 + c1 * zrel[None, :] + c2 * r[:, None]
+    rng = np.random.default_rng(4)
+    n = 200
+    rr = rng.uniform(GRID["dr"], (GRID["nr"] - 1) * GRID["dr"], n)
+    th = rng.uniform(0, 2 * np.pi, n)
+    zz = GRID["zmin"] + rng.uniform(0, (GRID["nz"] - 1) * GRID["dz"], n)
+    ex, ey, ez = _gather(Fm, rr * np.cos(th), rr * np.sin(th), zz)
+    np.testing.assert_allclose(ez, c0 + c1 * (zz - GRID["zmin"]) + c2 * rr, atol=1e-12)
+
+
+def test_boris_pure_electric_kick():
+    E = (0.3, -0.1, 0.5)
+    u = pt.boris(np.array([0.1]), np.array([0.2]), np.array([3.0]), *E, 0.0, 0.0, 0.0,
+                 -1.0, 1.0, 0.2)
+    eps = -1.0 * 0.2 / 2
+    np.testing.assert_allclose(np.array(u).ravel(), [0.1 + 2 * eps * E[0], 0.2 + 2 * eps * E[1],
+                                                     3.0 + 2 * eps * E[2]], rtol=1e-15)
+
+
+def test_boris_magnetic_rotation_angle():
+    # pure B along z: |u| conserved, u_perp rotates by exactly 2 atan(|t|) per step
+    ux, uy, uz = np.array([1.5]), np.array([0.0]), np.array([0.7])
+    Bz, q, m, dt = 2.0, -1.0, 1.0, 0.3
+    g = math.sqrt(1 + 1.5 ** 2 + 0.7 ** 2)
+    t = abs(q * dt / (2 * m) * Bz / g)
+    ang = 0.0
+    for _ in range(7):
+        nx, ny, nz = pt.boris(ux, uy, uz, 0, 0, 0, 0, 0, Bz, q, m, dt)
+        ang += math.atan2(ux[0] * ny[0] - uy[0] * nx[0], ux[0] * nx[0] + uy[0] * ny[0])
+        ux, uy, uz = nx, ny, nz
+    assert math.hypot(ux[0], uy[0]) == pytest.approx(1.5, rel=1e-14)
+    assert uz[0] == pytest.approx(0.7, rel=1e-15)
+    assert abs(ang) == pytest.approx(7 * 2 * math.atan(t), rel=1e-13)
+    # an electron (q < 0) gyrates counter-clockwise about +B
+    assert ang > 0
+
+
+def test_boris_exb_drift():
+    # E = Ex x^, B = Bz z^, |E| < |B|: the guiding centre drifts with E x B / B^2
+    Ex, Bz = 0.2, 1.0
+    ux, uy, uz = np.array([0.0]), np.array([0.0]), np.array([0.0])
+    x = y = 0.0
+    dt, nsteps = 0.05, 40000
+    for _ in range(nsteps):
+        ux, uy, uz = pt.boris(ux, uy, uz, Ex, 0.0, 0.0, 0.0, 0.0, Bz, -1.0, 1.0, dt)
+        g = math.sqrt(1 + ux[0] ** 2 + uy[0] ** 2 + uz[0] ** 2)
+        x += dt * ux[0] / g
+        y += dt * uy[0] / g
+    vd = y / (nsteps * dt)
+    # E x B / B^2 = (0, -Ex Bz, 0) / Bz^2
+    assert vd == pytest.approx(-Ex / Bz, rel=2e-2)
+    assert abs(x / (nsteps * dt)) < 1e-2
+
+
+def test_witness_peak_current_and_density(golden_dir):
+    # the Gaussian-bunch convention (sigma_x = sigma_y = rms width) reproduces
+    # the paper's printed 3 kA / 1e19 cm^-3 for its 50 pC witness
+    g = json.load(open(os.path.join(golden_dir, "witness_beam.json")))
+    n0 = g["n0_cm3"] * 1e6
+    _, kp = plasma_scales(n0)
+    w = charge_to_weight(g["charge_pC"] * 1e-12, 1000, n0)       # n0/kp^3 units
+    sz, sr = g["sigma_z_um"] * 1e-6 * kp, g["sigma_r_um"] * 1e-6 * kp
+    peak_n = 1000 * w / ((2 * np.pi) ** 1.5 * sz * sr * sr) * n0 / 1e6   # cm^-3
+    current = g["charge_pC"] * 1e-12 * 299792458.0 / (math.sqrt(2 * math.pi) * g["sigma_z_um"] * 1e-6)
+    tol = g["printed_precision"]
+    assert current / 1e3 == pytest.approx(g["peak_current_kA"], rel=tol)
+    assert peak_n == pytest.approx(g["peak_density_cm3"], rel=tol)

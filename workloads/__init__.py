@@ -1,0 +1,232 @@
+"""Seeded synthetic inputs shared by the HIP path, the oracle, the tests and the bench.
+
+This module only *generates inputs*: grid parameters, initial macro-particle
+positions/momenta/weights and random spectral test fields.  It holds none of
+the method's arithmetic (no deposit, transform, field update or push), so it
+may be imported by both the product path and the oracle without coupling them.
+
+Units are normalized plasma units: lengths in 1/k_p, time in 1/omega_p,
+momenta u = gamma*beta, densities in n0, charges in e, masses in m_e.  The
+workloads follow the beam-plasma setup of the paper's simulation section
+(cold drive and witness electron bunches in a uniform plasma sampled with
+2 x 2 x 4 macro-particles per cell in (z, r, theta), two azimuthal modes,
+dt = dz / c); the sizes are the ones of the workload presets below.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+# CODATA 2018 exact / recommended values (SI)
+E_CHARGE = 1.602176634e-19
+M_E = 9.1093837015e-31
+EPS0 = 8.8541878128e-12
+C_LIGHT = 299792458.0
+
+# kperp grid choices (mirrors the enum of the C interface)
+KPERP_J0_ZEROS = 0   # every mode: zeros of J_0 / R
+KPERP_SINE = 1       # every mode: (i + 1) * pi / R
+KPERP_JM_ZEROS = 2   # mode m: zeros of J_m / R (ill-conditioned for m = 1)
+
+
+def plasma_scales(n0_m3: float) -> Tuple[float, float]:
+    """Return (omega_p [1/s], k_p [1/m]) for an electron density n0 [1/m^3]."""
+    wp = math.sqrt(n0_m3 * E_CHARGE ** 2 / (EPS0 * M_E))
+    return wp, wp / C_LIGHT
+
+
+def charge_to_weight(charge_C: float, n_macro: int, n0_m3: float) -> float:
+    """Macro-particle weight (in units of n0 / k_p^3) of a bunch of total
+    charge |charge_C| split into n_macro equal macro-particles."""
+    _, kp = plasma_scales(n0_m3)
+    n_phys = abs(charge_C) / E_CHARGE
+    return n_phys / n_macro * kp ** 3 / n0_m3
+
+
+@dataclasses.dataclass
+class Species:
+    name: str
+    q: float                 # charge in units of e
+    m: float                 # mass in units of m_e
+    mobile: bool
+    x: np.ndarray            # float64
+    y: np.ndarray
+    z: np.ndarray
+    ux: np.ndarray           # float32, gamma * beta
+    uy: np.ndarray
+    uz: np.ndarray
+    w: np.ndarray            # float32, macro-particle weight (n0 / k_p^3 units)
+    inject: bool = False     # re-created as a lattice column at the head when the window moves
+    ppc: Tuple[int, int, int] = (2, 2, 4)
+    density: float = 1.0     # lattice density in units of n0 (for injection)
+    diag: bool = False       # beam species reported by the diagnostics
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    def copy(self) -> "Species":
+        return dataclasses.replace(self, **{k: getattr(self, k).copy() for k in
+                                            ("x", "y", "z", "ux", "uy", "uz", "w")})
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nz: int
+    nr: int
+    n_modes: int
+    order: int               # stencil order p = 2n; 0 means infinite order
+    dz: float
+    dr: float
+    dt: float
+    zmin: float
+    moving_window: bool
+    kperp_grid: int
+    steps: int
+    species: List[Species]
+    n0_m3: float = 1e23
+
+    @property
+    def n_mobile(self) -> int:
+        return sum(s.n for s in self.species if s.mobile)
+
+    def copy(self) -> "Workload":
+        return dataclasses.replace(self, species=[s.copy() for s in self.species])
+
+
+def lattice(nz: int, nr: int, dz: float, dr: float, zmin: float,
+            ppc: Tuple[int, int, int] = (2, 2, 4), density: float = 1.0,
+            j_range: Optional[Tuple[int, int]] = None) -> Dict[str, np.ndarray]:
+    """Cold uniform lattice with ppc = (pz, pr, pt) macro-particles per cell.
+
+    Cell (j, i) holds particles at z = zmin + (j + (a + 1/2)/pz) dz,
+    r = (i + (b + 1/2)/pr) dr, theta = 2 pi l / pt; the weight is the
+    sub-cell volume r (dr/pr)(dz/pz)(2 pi/pt) times the density.
+    """
+    pz, pr, pt = ppc
+    j0, j1 = (0, nz) if j_range is None else j_range
+    j = np.arange(j0, j1, dtype=np.float64)
+    i = np.arange(nr, dtype=np.float64)
+    a = (np.arange(pz) + 0.5) / pz
+    b = (np.arange(pr) + 0.5) / pr
+    th = 2.0 * np.pi * np.arange(pt) / pt
+    # ordering: z-cell outermost, then r-cell, then sub-positions (cell-sorted)
+    J, A, I, B, T = np.meshgrid(j, a, i, b, th, indexing="ij")
+    z = zmin + (J + A) * dz
+    r = (I + B) * dr
+    x = r * np.cos(T)
+    y = r * np.sin(T)
+    w = density * r * (dr / pr) * (dz / pz) * (2.0 * np.pi / pt)
+    # reorder so that all particles of one (j, i) cell are contiguous
+    perm = np.transpose(np.arange(J.size).reshape(J.shape), (0, 2, 1, 3, 4)).ravel()
+    out = {
+        "x": x.ravel()[perm].astype(np.float64),
+        "y": y.ravel()[perm].astype(np.float64),
+        "z": z.ravel()[perm].astype(np.float64),
+        "w": w.ravel()[perm].astype(np.float32),
+    }
+    n = out["x"].shape[0]
+    for k in ("ux", "uy", "uz"):
+        out[k] = np.zeros(n, dtype=np.float32)
+    return out
+
+
+def gaussian_bunch(n: int, charge_C: float, gamma: float, sigma_r: float, sigma_z: float,
+                   z_center: float, seed: int, n0_m3: float = 1e23) -> Dict[str, np.ndarray]:
+    """Cold Gaussian electron bunch (sigma_x = sigma_y = sigma_r) moving along +z."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.normal(0.0, sigma_r, n)
+    y = rng.normal(0.0, sigma_r, n)
+    z = rng.normal(z_center, sigma_z, n)
+    uz = math.sqrt(gamma * gamma - 1.0)
+    w = charge_to_weight(charge_C, n, n0_m3)
+    return {
+        "x": x.astype(np.float64), "y": y.astype(np.float64), "z": z.astype(np.float64),
+        "ux": np.zeros(n, np.float32), "uy": np.zeros(n, np.float32),
+        "uz": np.full(n, uz, np.float32), "w": np.full(n, w, np.float32),
+    }
+
+
+def _plasma_species(nz, nr, dz, dr, zmin, ppc=(2, 2, 4)):
+    lat = lattice(nz, nr, dz, dr, zmin, ppc)
+    ele = Species("plasma_e", -1.0, 1.0, True, inject=True, ppc=ppc, **lat)
+    ion_lat = {k: v.copy() for k, v in lat.items()}
+    ion = Species("plasma_ion", +1.0, 1836.15267343, False, inject=True, ppc=ppc, **ion_lat)
+    return ele, ion
+
+
+def _bunch_species(name, n, charge_C, gamma, sigma_r, sigma_z, zc, seed, diag):
+    b = gaussian_bunch(n, charge_C, gamma, sigma_r, sigma_z, zc, seed)
+    return Species(name, -1.0, 1.0, True, diag=diag, **b)
+
+
+def preset(name: str, seed: int = 0) -> Workload:
+    """Workload presets.
+
+    * ``c0``    256 x 64 cells, 2 modes, p = 16, dz = dr = 0.05, 1e4-particle
+                100 pC drive bunch (gamma 1000, sigma 0.5), 50 steps.
+    * ``c1``    2048 x 256 cells, 2 modes, p = 32, dz = 0.02, dr = 0.05, 1 nC drive
+                (1e6 particles) + 50 pC witness (2e5 particles), gamma 2000.
+    * ``tiny``  32 x 16 cells, 2 modes, p = 8, a 64-particle bunch: test-sized.
+    * ``small`` 128 x 32 cells, 2 modes, p = 16, plasma + bunch: several tiles,
+                ragged particle counts; the oracle finishes in seconds.
+    """
+    if name == "c0":
+        nz, nr, dz, dr = 256, 64, 0.05, 0.05
+        zmin = 0.0
+        ele, ion = _plasma_species(nz, nr, dz, dr, zmin)
+        drive = _bunch_species("drive", 10_000, 100e-12, 1000.0, 0.5, 0.5,
+                               zmin + 0.7 * nz * dz, seed, True)
+        return Workload("c0", nz, nr, 2, 16, dz, dr, dz, zmin, True, KPERP_J0_ZEROS, 50,
+                        [ele, ion, drive])
+    if name == "c1":
+        nz, nr, dz, dr = 2048, 256, 0.02, 0.05
+        zmin = 0.0
+        ele, ion = _plasma_species(nz, nr, dz, dr, zmin)
+        zd = zmin + 0.7 * nz * dz
+        drive = _bunch_species("drive", 1_000_000, 1e-9, 2000.0, 0.5, 0.5, zd, seed, False)
+        wit = _bunch_species("witness", 200_000, 50e-12, 2000.0, 0.1, 0.1, zd - 4.0,
+                             seed + 1, True)
+        return Workload("c1", nz, nr, 2, 32, dz, dr, dz, zmin, True, KPERP_J0_ZEROS, 2000,
+                        [ele, ion, drive, wit])
+    if name == "tiny":
+        nz, nr, dz, dr = 32, 16, 0.1, 0.1
+        zmin = 0.0
+        b = _bunch_species("bunch", 64, 20e-12, 50.0, 0.3, 0.4, 1.6, seed, True)
+        return Workload("tiny", nz, nr, 2, 8, dz, dr, dz, zmin, False, KPERP_J0_ZEROS, 4, [b])
+    if name == "small":
+        nz, nr, dz, dr = 128, 32, 0.05, 0.05
+        zmin = 0.0
+        ele, ion = _plasma_species(nz, nr, dz, dr, zmin)
+        drive = _bunch_species("drive", 3001, 50e-12, 500.0, 0.3, 0.4,
+                               zmin + 0.6 * nz * dz, seed, True)
+        return Workload("small", nz, nr, 2, 16, dz, dr, dz, zmin, True, KPERP_J0_ZEROS, 10,
+                        [ele, ion, drive])
+    raise KeyError(name)
+
+
+def random_spectral(shape, seed: int) -> np.ndarray:
+    """Seeded complex128 array with standard-normal real and imaginary parts."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def random_particles(n: int, nz: int, nr: int, dz: float, dr: float, zmin: float,
+                     seed: int, u_scale: float = 1.0) -> Dict[str, np.ndarray]:
+    """Seeded particles spread uniformly over the box (r up to nr * dr, any z)
+    with random momenta and weights: used by deposit/gather/push parity tests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = np.sqrt(rng.uniform(0.0, 1.0, n)) * nr * dr
+    th = rng.uniform(0.0, 2.0 * np.pi, n)
+    z = zmin + rng.uniform(0.0, nz * dz, n)
+    return {
+        "x": r * np.cos(th), "y": r * np.sin(th), "z": z,
+        "ux": (u_scale * rng.standard_normal(n)).astype(np.float32),
+        "uy": (u_scale * rng.standard_normal(n)).astype(np.float32),
+        "uz": (u_scale * rng.standard_normal(n)).astype(np.float32),
+        "w": rng.uniform(0.5, 1.5, n).astype(np.float32),
+    }
