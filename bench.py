@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput of the quasi-cylindrical order-p PSATD PIC cycle on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0]
+
+A step is one whole PIC cycle (gather + Boris push, cell sort, tile deposit,
+forward z-FFT + Hankel transform, current correction + PSATD, inverse
+transforms, moving window with injection) over the synthetic beam-plasma
+workload, everything resident in HBM.  W untimed steps (to reach the blown-out
+wake) are followed by K timed steps.  One JSON line is printed:
+
+  value       = mobile macro-particles x K / wall time  (particle-pushes/s)
+  roofline    = the kernel with the largest GPU time, its algorithmic bytes
+                (or flops) per launch over its average HIP-event duration
+  cpu_baseline= the FP64 oracle on the host cores, one step on a 1/8
+                subsample of the same workload, in the same unit
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+MFMA_FP32_TFLOPS = 157.3       # MI355X dense FP32 matrix
+MFMA_BF16_TFLOPS = 2500.0      # dense bf16 / fp16
+
+# algorithmic traffic per unit of work (bytes), see the design doc
+BYTES_PER_PARTICLE = {
+    "gather_push": 78.0,   # read x,y,z (24) + u (12); write 36; field share ~6
+    "sort": 86.0,          # read key (4) + particle (41); write particle (41)
+    "deposit": 45.0,       # read x,y,z (24) + u (12) + w (4); grid share ~5
+}
+BYTES_PER_CELL = {
+    "fft_fwd": 16.0,       # read + write one complex64 per cell and transform
+    "fft_inv": 16.0,
+    "psatd": 160.0,        # read 11 complex + write 6 complex (E, B) + 3 (J) per cell and mode
+}
+
+WORKLOAD_TEXT = {
+    "c1": ("beam-driven plasma wakefield at production size: 2048 x 256 cells, 2 azimuthal "
+           "modes, stencil order p = 32, dz = 0.02/kp, dr = 0.05/kp, dt = dz/c, moving window; "
+           "8,388,608 plasma electrons (2x2x4 per cell) + as many immobile ions; 1e6-particle "
+           "1 nC drive and 2e5-particle 50 pC witness, gamma 2000"),
+    "c0": ("256 x 64 cells, 2 modes, p = 16, dz = dr = 0.05/kp, moving window; 262,144 plasma "
+           "electrons (2x2x4 per cell) + immobile ions; 1e4-particle 100 pC drive, gamma 1000"),
+}
+
+
+def _phase_units(name, wl, n_part, prec):
+    """(algorithmic amount per launch, unit, bound, peak) of one timed phase."""
+    M, nr, nz = wl.n_modes, wl.nr, wl.nz
+    cells = M * nr * nz
+    if name in BYTES_PER_PARTICLE:
+        return BYTES_PER_PARTICLE[name] * n_part / 1e9, "GB/s", "hbm", HBM_PEAK_GBS
+    if name == "fft_fwd":
+        return BYTES_PER_CELL[name] * 5 * cells / 1e9, "GB/s", "hbm", HBM_PEAK_GBS
+    if name == "fft_inv":
+        return BYTES_PER_CELL[name] * 6 * cells / 1e9, "GB/s", "hbm", HBM_PEAK_GBS
+    if name == "psatd":
+        return BYTES_PER_CELL[name] * nr * nz * M / 1e9, "GB/s", "hbm", HBM_PEAK_GBS
+    if name in ("dht_fwd", "dht_inv"):
+        batch = (5 if name == "dht_fwd" else 6) * M
+        flops = 2.0 * nr * nr * (2 * nz) * batch
+        peak = MFMA_FP32_TFLOPS if prec == 0 else MFMA_BF16_TFLOPS
+        return flops / 1e12, "TFLOP/s", "mfma", peak
+    return None
+
+
+def _kernel_sources_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1611_05712_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel, workload):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/traffic.json),
+    valid only while the kernel sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    e = d.get(workload, {}).get(kernel)
+    if not e or e.get("sources") != _kernel_sources_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(wl_name, stride=8):
+    """The oracle (never tuned) timed for one PIC step on every `stride`-th
+    macro-particle of the workload, in particle-pushes/s."""
+    from oracle.cycle import OracleSim
+    from workloads import preset
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()
+                    if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        blas = 1
+    wl = preset(wl_name)
+    for s in wl.species:
+        for a in ("x", "y", "z", "ux", "uy", "uz", "w"):
+            setattr(s, a, getattr(s, a)[::stride].copy())
+        s.w = (s.w * stride).astype(s.w.dtype)
+    n_mobile = wl.n_mobile
+    o = OracleSim(wl)
+    t0 = time.perf_counter()
+    o.step(1)
+    dt = time.perf_counter() - t0
+    return {"value": n_mobile / dt, "unit": "particle-pushes/s", "cores": int(blas),
+            "kind": "oracle",
+            "sample": (f"one full PIC step of the {wl_name} grid with every {stride}th macro-particle "
+                       f"({n_mobile} mobile, weights x{stride}); {dt:.1f} s; particle loops are "
+                       f"single-threaded NumPy, Hankel products use {blas} BLAS threads")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--hankel-prec", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the z-slab decomposition is described in DESIGN.md); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1611_05712_amd import Simulation
+    from workloads import preset
+
+    prec = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}[args.hankel_prec]
+    wl = preset(args.workload)
+    sim = Simulation.from_workload(wl, hankel_prec=prec, device="cuda:0")
+    t0 = time.perf_counter()
+    sim.step(args.warmup)
+    sim.sync()
+    warm_s = time.perf_counter() - t0
+    n_before = sim.num_particles()
+
+    sim.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = sim.timing_read()
+    sim.timing_enable(False)
+    n_after = sim.num_particles()
+    n_part = 0.5 * (n_before + n_after)
+
+    cells = wl.nz * wl.nr * wl.n_modes
+    spectral_ms = sum(times[k][0] for k in ("fft_fwd", "dht_fwd", "psatd", "dht_inv", "fft_inv",
+                                             "window"))
+    kernels = {}
+    for name, (tot_ms, nl) in times.items():
+        if nl == 0:
+            continue
+        avg_s = tot_ms / nl / 1e3
+        u = _phase_units(name, wl, n_part, prec)
+        entry = {"ms_per_launch": round(tot_ms / nl, 5), "launches": nl,
+                 "share": round(tot_ms / max(1e-9, sum(t for t, _ in times.values())), 4)}
+        if u:
+            amount, unit, bound, peak = u
+            ach = amount / avg_s
+            entry.update({"achieved": round(ach, 2), "unit": unit, "bound": bound,
+                          "frac": round(ach / peak, 4)})
+        kernels[name] = entry
+    dominant = max((k for k in kernels if "achieved" in kernels[k]),
+                   key=lambda k: times[k][0])
+    d = kernels[dominant]
+    peak = _phase_units(dominant, wl, n_part, prec)[3]
+    roofline = {"kernel": dominant, "bound": d["bound"], "achieved": d["achieved"], "peak": peak,
+                "unit": d["unit"], "frac": d["frac"],
+                "traffic": _traffic(dominant, args.workload)}
+
+    out = {
+        "metric": "particle-pushes/s (whole PIC cycle) & field cell-updates/s on 1 GPU",
+        "value": n_part * args.steps / wall,
+        "unit": "particle-pushes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
+                   "mobile_particles": int(n_part), "cells_per_mode": wl.nz * wl.nr,
+                   "modes": wl.n_modes, "order": wl.order,
+                   "hankel_prec": args.hankel_prec, "positions": "f64"},
+        "field_cell_updates_per_s": cells * args.steps / (spectral_ms / 1e3) if spectral_ms else None,
+        "roofline": roofline,
+        "kernels": kernels,
+        "warmup_s": round(warm_s, 3),
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

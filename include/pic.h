@@ -1,0 +1,261 @@
+/*
+ * pic.h -- C interface of the MI355X (gfx950) quasi-cylindrical, arbitrary-order
+ * PSATD particle-in-cell cycle.
+ *
+ * Method: Jalas et al., "Accurate modeling of plasma acceleration with arbitrary
+ * order pseudo-spectral particle-in-cell methods".  One PIC cycle per azimuthal
+ * mode m is
+ *   (a) linear-shape deposit of rho and J onto the (r, z) grid of each mode,
+ *   (b) FFT along z and discrete Hankel transform along r
+ *       (Sec. "Finite order pseudo-spectral solvers", the quasi-cylindrical
+ *       decomposition into spectral +, -, z components),
+ *   (c) PSATD update of E and B, Eqs. (1a)-(1b) with the operators of
+ *       Eqs. (2a)-(2b) and k_z replaced by the modified wavenumber [k_z] of
+ *       Eq. (5) everywhere, including inside |k|, C and S,
+ *   (d) inverse transforms,
+ *   (e) field gather and Boris push.
+ *
+ * Units: normalized plasma units (lengths 1/k_p, time 1/omega_p, u = gamma*beta,
+ * densities n0, charge e, mass m_e; c = 1).
+ *
+ * Conventions shared by every entry point
+ *   - Fields of mode m are complex; the real field is
+ *     F = sum_{m=-M..M} F_m exp(-i m theta) with F_{-m} = conj(F_m).
+ *     Vector fields are stored as F_+ = (F_r - i F_theta)/2, F_- = (F_r + i F_theta)/2
+ *     and F_z; their Hankel orders in mode m are m+1, m-1 and m.
+ *   - Grid nodes: z_j = z_min + j dz (periodic in z, j = 0..nz-1),
+ *     r_i = (i + 1/2) dr (i = 0..nr-1).  Host field buffers are [nr][nz]
+ *     complex float32 (interleaved re, im; z fastest).  Spectral buffers are
+ *     [nr (k_perp index)][nz (FFT order along k_z)].
+ *   - Every call returns a status (PIC_OK = 0 or a negative pic_status); no
+ *     exception or abort crosses the interface.  Work is enqueued on the stream
+ *     given to pic_init; errors of asynchronous GPU work surface at the next
+ *     synchronizing call (pic_diagnostics, pic_get_*, pic_set_field, pic_sync,
+ *     pic_free) as PIC_EHIP.
+ *   - Memory: the caller owns one device workspace of pic_workspace_bytes()
+ *     bytes (any device allocation, e.g. a torch uint8 tensor) that must stay
+ *     alive and untouched until pic_free; the library allocates no device
+ *     memory of its own.  Host pointers passed in are only read during the call.
+ *   - Calls on one context must not overlap (one host thread at a time).
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_EINVAL = -1,    /* invalid configuration, species or pointer */
+  PIC_ENOSPC = -2,    /* workspace too small, or particle capacity exceeded */
+  PIC_EHIP = -3,      /* HIP runtime error (launch or asynchronous fault) */
+  PIC_ESTATE = -4,    /* call out of order (see the step order below) */
+  PIC_ENUMERIC = -5   /* NaN or Inf found by pic_diagnostics */
+} pic_status;
+
+/* Radial wavenumber grid of the discrete Hankel transform. */
+typedef enum {
+  PIC_KPERP_J0_ZEROS = 0, /* k_i = j_{0,i} / R for every mode (default) */
+  PIC_KPERP_SINE = 1,     /* k_i = (i + 1) pi / R */
+  PIC_KPERP_JM_ZEROS = 2  /* k_i = j_{m,i} / R for mode m */
+} pic_kperp_grid;
+
+/* Arithmetic of the Hankel-transform matrix products. */
+typedef enum {
+  PIC_H_FP32 = 0,   /* FP32 MFMA, FP32 operands */
+  PIC_H_BF16X3 = 1, /* split hi+lo bfloat16 operands, 3 MFMA products, FP32 accumulate */
+  PIC_H_FP16X3 = 2  /* split hi+lo float16 operands, 3 MFMA products, FP32 accumulate */
+} pic_hankel_prec;
+
+/* Field components addressed by pic_get_field / pic_set_field. */
+typedef enum {
+  PIC_E_PLUS = 0, PIC_E_MINUS = 1, PIC_E_Z = 2,
+  PIC_B_PLUS = 3, PIC_B_MINUS = 4, PIC_B_Z = 5,
+  PIC_J_PLUS = 6, PIC_J_MINUS = 7, PIC_J_Z = 8,
+  PIC_RHO_OLD = 9,   /* rho^n   (deposited at x^n)      */
+  PIC_RHO_NEW = 10,  /* rho^{n+1} (deposited at x^{n+1}) */
+  PIC_N_COMP = 11
+} pic_comp;
+
+typedef struct pic_ctx pic_ctx;
+
+typedef struct {
+  int32_t nz;          /* cells along z: power of two, 64 <= nz <= 4096 */
+  int32_t nr;          /* radial cells: multiple of 32, 32 <= nr <= 1024 */
+  int32_t n_modes;     /* azimuthal modes m = 0..n_modes-1, 1 <= n_modes <= 4 */
+  int32_t order;       /* stencil order p = 2n (even, >= 2); 0 = infinite order */
+  double dz, dr, dt;   /* > 0 */
+  double z_min;        /* position of node j = 0 at step 0 */
+  int32_t moving_window;      /* 1: z_min advances by dz after every step (needs dt == dz) */
+  int32_t kperp_grid;         /* pic_kperp_grid */
+  int32_t hankel_prec;        /* pic_hankel_prec */
+  int32_t current_correction; /* 1 (default); 0 disables the spectral correction */
+} pic_config;
+
+typedef struct {
+  int64_t n;          /* macro-particles (may be 0) */
+  double q, m;        /* charge (units of e, nonzero) and mass (units of m_e, > 0) */
+  int32_t mobile;     /* 0: immobile background, deposited into rho only.  With a
+                         moving window an immobile species must be uniform in z
+                         (a lattice with a one-cell period), else PIC_EINVAL */
+  int32_t inject;     /* 1: a cold lattice column is injected at the head at every
+                         window move (ppc_z x ppc_r x ppc_t particles per cell at
+                         z = (j + (a+1/2)/ppc_z) dz, r = (i + (b+1/2)/ppc_r) dr,
+                         theta = 2 pi l / ppc_t, weight density * r dr dz 2pi/(ppc_z ppc_r ppc_t)) */
+  int32_t ppc_z, ppc_r, ppc_t;
+  double density;     /* injected lattice density (units of n0) */
+  int32_t diag;       /* 1: species selectable by pic_diagnostics */
+  const double *x, *y, *z;            /* host, length n */
+  const float *ux, *uy, *uz, *w;      /* host, length n; w = macro-particle weight */
+} pic_species;
+
+/* Bytes of device workspace needed for cfg, the species and a particle capacity
+ * of max_particles mobile macro-particles (0 = total mobile count + 12.5 %).
+ * Errors: PIC_EINVAL (bad cfg / species / null pointer). */
+int pic_workspace_bytes(const pic_config* cfg, const pic_species* species, int n_species,
+                        int64_t max_particles, size_t* bytes);
+
+/* Builds a context: validates, carves the workspace, builds in FP64 on the GPU
+ * the [k_z] table (Eq. (5)), the k_perp grid and the Hankel matrices
+ * (B_nu[i_r][i_k] = J_nu(k r), F_nu = B_nu^{-1} by Gauss-Jordan elimination),
+ * uploads the particles, deposits the immobile background and zeroes E, B.
+ * `hip_stream` is a hipStream_t (NULL = default stream).  Synchronizes once.
+ * Errors: PIC_EINVAL, PIC_ENOSPC (workspace too small), PIC_EHIP. */
+int pic_init(const pic_config* cfg, const pic_species* species, int n_species,
+             int64_t max_particles, void* workspace, size_t bytes, void* hip_stream,
+             pic_ctx** out);
+
+/* Step order: gather_push -> deposit -> spectral_push, repeated.  Any other
+ * order returns PIC_ESTATE.  Particle storage order changes at every deposit. */
+
+/* Gathers E^n, B^n at x^n (linear shapes, 4 nodes per mode), Boris-pushes
+ * u^{n-1/2} -> u^{n+1/2} and moves x^{n+1} = x^n + dt u/gamma. */
+int pic_gather_push(pic_ctx* ctx);
+
+/* Sorts the particles by cell, then deposits rho^n at x^n, J^{n+1/2} at
+ * x^{n+1/2} with v^{n+1/2} and rho^{n+1} at x^{n+1}; the immobile background
+ * density is added node by node to both densities.  Atomic-free at global
+ * scope: each grid tile is written once by the workgroup that owns it. */
+int pic_deposit(pic_ctx* ctx);
+
+/* Forward FFT along z and Hankel transform of J, rho^n, rho^{n+1}; spectral
+ * current correction (J += grad F, F = (div J + (rho^{n+1}-rho^n)/dt)/k^2);
+ * PSATD update of the spectral E, B; inverse transforms to real space; then,
+ * with a moving window, shifts the fields one cell toward the tail (head column
+ * zeroed), advances z_min, drops particles behind it and injects lattice columns
+ * at the head. */
+int pic_spectral_push(pic_ctx* ctx);
+
+/* n x (gather_push, deposit, spectral_push). */
+int pic_step(pic_ctx* ctx, int n);
+
+/* Waits for all enqueued work; reports asynchronous errors as PIC_EHIP. */
+int pic_sync(pic_ctx* ctx);
+
+typedef struct {
+  int32_t species;        /* index into the pic_init species array (must have diag = 1) */
+  double slice_len;       /* slice length (1/k_p) */
+  double n_sigma;         /* slices cover |z - <z>| <= n_sigma * sigma_z */
+  int32_t min_per_slice;  /* slices with fewer macro-particles are skipped */
+} pic_diag_req;
+
+typedef struct {
+  double eps_nx, eps_ny;          /* normalized rms emittances sqrt(<x^2><ux^2> - <x ux>^2) */
+  double mean_gamma, sigma_gamma; /* weighted mean and rms of gamma */
+  double mean_slice_sigma_gamma;  /* average over kept slices of the slice rms gamma */
+  double z_mean, sigma_z;
+  int64_t n;                      /* macro-particles of the species inside the window */
+  int32_t n_slices, nan_flag;
+} pic_diag_out;
+
+/* Beam diagnostics of one species (weighted, central moments accumulated in
+ * FP64): the quantities behind the paper's Err_eps and Err_sigma_gamma,
+ * Eqs. (11)-(12).  Synchronizes.  Returns PIC_ENUMERIC (with out filled and
+ * nan_flag = 1) if a position or momentum of the species is not finite. */
+int pic_diagnostics(pic_ctx* ctx, const pic_diag_req* req, pic_diag_out* out);
+
+/* Copies one field component of one mode to host memory ([nr][nz] complex
+ * float32, 8*nr*nz bytes).  spectral = 0: real space; 1: spectral.  E, B are
+ * the current fields; J, rho are those of the last deposit (spectral J is after
+ * the current correction).  Synchronizes.  Errors: PIC_EINVAL. */
+int pic_get_field(pic_ctx* ctx, int mode, int comp, int spectral, void* host_dst);
+
+/* Overwrites one real-space field component of one mode from host memory
+ * ([nr][nz] complex float32).  Setting E or B makes the next spectral_push
+ * re-transform the real-space E, B; setting all five source components
+ * (J_+, J_-, J_z, rho^n, rho^{n+1}) of every mode allows spectral_push without a
+ * deposit.  Synchronizes.  Errors: PIC_EINVAL. */
+int pic_set_field(pic_ctx* ctx, int mode, int comp, const void* host_src);
+
+/* Number of live mobile macro-particles (inside the window).  Synchronizes. */
+int pic_num_particles(pic_ctx* ctx, int64_t* n);
+
+/* Copies the live mobile particles of one species (index into the pic_init
+ * array) to host: xyz = n*3 doubles (x, y, z per particle), uvw = n*3 floats,
+ * w = n floats (may be NULL); at most `cap` particles, count in *n.
+ * Order is the library's current storage order.  Synchronizes. */
+int pic_get_particles(pic_ctx* ctx, int species, int64_t cap, double* xyz, float* uvw,
+                      float* w, int64_t* n);
+
+/* Current window position z_min and number of completed steps. */
+int pic_get_state(pic_ctx* ctx, double* z_min, int64_t* steps);
+
+/* Frees the host-side context (the workspace stays the caller's).  Synchronizes. */
+int pic_free(pic_ctx* ctx);
+
+/* Static description of a status code. */
+const char* pic_strerror(int status);
+
+/* --------------------------------------------------------------------------
+ * Kernel timing (measurement support): when enabled, HIP events are recorded
+ * on the context's stream around each phase of the cycle; pic_timing_read
+ * synchronizes and returns the summed GPU time and launch count of a phase
+ * since the last pic_timing_enable.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+  PIC_T_GATHER_PUSH = 0, /* gather + Boris push kernel */
+  PIC_T_SORT = 1,        /* bucket scan + scatter */
+  PIC_T_DEPOSIT = 2,     /* tile deposit kernel */
+  PIC_T_FFT_FWD = 3,     /* forward z-FFT of the sources (and of E, B when re-transformed) */
+  PIC_T_DHT_FWD = 4,     /* forward Hankel-transform products */
+  PIC_T_PSATD = 5,       /* window shift + current correction + PSATD update */
+  PIC_T_DHT_INV = 6,     /* inverse Hankel-transform products of E, B */
+  PIC_T_FFT_INV = 7,     /* inverse z-FFT of E, B (+ window shift) */
+  PIC_T_WINDOW = 8,      /* departed-column transform, window advance, injection */
+  PIC_T_N = 9
+} pic_timer;
+
+/* enable != 0 clears previous records and starts recording; 0 stops. */
+int pic_timing_enable(pic_ctx* ctx, int enable);
+/* Errors: PIC_EINVAL (bad timer), PIC_EHIP. */
+int pic_timing_read(pic_ctx* ctx, int timer, double* total_ms, int64_t* launches);
+
+/* --------------------------------------------------------------------------
+ * Kernel-level entry points used by parity tests and benchmarks.  Each runs
+ * one step of the cycle on caller-provided device buffers (no context), on
+ * `hip_stream`, asynchronously.  Pointers are device pointers.
+ * ------------------------------------------------------------------------ */
+
+/* Batched complex FFT along the contiguous axis: `rows` rows of nz complex
+ * float32, in place.  inverse = 0: X_k = sum_j x_j exp(-2 pi i j k / nz);
+ * inverse = 1: x_j = (1/nz) sum_k X_k exp(+2 pi i j k / nz).  nz is a power of
+ * two in [16, 4096].  Errors: PIC_EINVAL. */
+int pic_fft_z(void* data, int64_t rows, int nz, int inverse, void* hip_stream);
+
+/* Batched real matrix product Y_b = A_b X_b of `batch` pairs: A_b is n x n
+ * float32 stored TRANSPOSED (at[k][m] = A[m][k]), X_b and Y_b are n x ncols
+ * float32 row-major (a complex [n][nz] field is the real n x 2nz matrix).
+ * a_t[b], x[b], y[b] are device arrays of `batch` device pointers.
+ * prec = pic_hankel_prec.  n is a multiple of 32, ncols a multiple of 128.
+ * Errors: PIC_EINVAL. */
+int pic_dht_gemm(const void* const* a_t, const void* const* x, void* const* y, int batch,
+                 int n, int ncols, int prec, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

@@ -1,0 +1,913 @@
+// C interface of the quasi-cylindrical order-p PSATD PIC cycle (see include/pic.h).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "common.h"
+#include "launch.h"
+
+using namespace pic;
+
+// records the first HIP error of a sequence into `rc`
+#define PIC_CK(expr)                                          \
+  do {                                                        \
+    if ((expr) != hipSuccess && rc == PIC_OK) rc = PIC_EHIP; \
+  } while (0)
+
+namespace pic {
+
+__global__ void k_fill_zero(uint32_t* p, size_t nwords) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < nwords; i += stride) p[i] = 0u;
+}
+
+void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  size_t nw = (bytes + 3) / 4;
+  if (nw == 0) return;
+  size_t nb = (nw + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, s, (uint32_t*)p, nw);
+}
+
+__global__ void k_window_advance(DevState* st, double zmin0, double dz) {
+  st->n_shift += 1;
+  st->zmin = zmin0 + (double)st->n_shift * dz;
+}
+
+__global__ void k_state_init(DevState* st, double zmin, int n_part) {
+  st->zmin = zmin;
+  st->n_shift = 0;
+  st->n_part = n_part;
+  st->n_live = n_part;
+  st->pending_shift = 0;
+  st->overflow = 0;
+}
+
+__global__ void k_set_npart(DevState* st, int n) {
+  st->n_part = n;
+  st->n_live = n;
+}
+
+// F <- exp(+i k_z dz) (F - tailhat) on the spectral E, B of every mode
+__global__ void k_apply_shift(float2* spec, const float2* tw, const float2* tailhat, int nz, int nr, int M) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t plane = (int64_t)nr * nz;
+  if (idx >= 6 * M * plane) return;
+  int64_t cm = idx / plane;           // c*M + m
+  int64_t cell = idx % plane;
+  int ik = (int)(cell / nz), iz = (int)(cell % nz);
+  float2 ph = cconj(tw[iz]);
+  spec[idx] = cmul(ph, csub(spec[idx], tailhat[cm * nr + ik]));
+}
+
+}  // namespace pic
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct SpeciesInfo {
+  double q, m;
+  int mobile, inject, ppc_z, ppc_r, ppc_t, diag;
+  double density;
+  int64_t n;
+};
+
+struct pic_ctx {
+  pic_config cfg;
+  hipStream_t stream;
+  Grid g;
+  int M, nz, nr;
+  int64_t cap;
+  int n_species;
+  SpeciesInfo sp[kMaxSpecies];
+  SpeciesConst sc;
+  InjectTable inj;
+  int hz, hr;
+  int gemm_bm;
+  DepositShape dep;
+  // device
+  DevState* st;
+  Parts parts[2];
+  int cur;
+  uint32_t* key;
+  int *count, *offset, *cursor, *bsum;
+  int *dep_nchunk, *dep_start;
+  float2* dep_partial;
+  float2 *real, *spec, *tmp, *bg, *tail, *tailhat;   // bg: real-space immobile density [m][r][z]
+  double *kz, *kzm, *kperp;
+  float2* tw;
+  float* mats;           // [m][order slot 0..2][dir 0 fwd / 1 bwd][nr][nr], transposed
+  double* setup64;
+  const float** ptr_tab; // device pointer tables (see init)
+  double *diag_partial, *diag_out, *diag_slices;
+  int* misc;             // [0] GJ fail, [1..2] uniform check, [3] counter
+  bool have_bg;
+  // host mirrors
+  int phase;             // 0: expect gather_push, 1: expect deposit, 2: expect spectral_push
+  bool eb_stale;
+  bool spec_pending;
+  uint32_t src_set[kMaxModes];
+  int64_t steps;
+  int64_t n_shift;
+  // timing
+  bool timing;
+  std::vector<hipEvent_t> ev_pool;
+  struct Rec { int phase; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  size_t ev_used;
+  // pointer-table offsets (entries of ptr_tab)
+  int pt_fwd_src, pt_fwd_eb, pt_inv_eb, pt_tail;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxSlices = 16384;
+
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int validate(const pic_config* c, const pic_species* s, int ns) {
+  if (!c) return PIC_EINVAL;
+  if (!is_pow2(c->nz) || c->nz < 64 || c->nz > 4096) return PIC_EINVAL;
+  if (c->nr < 32 || c->nr > 1024 || (c->nr % 32)) return PIC_EINVAL;
+  if (c->n_modes < 1 || c->n_modes > kMaxModes) return PIC_EINVAL;
+  if (c->order < 0 || (c->order % 2) || c->order == 1) return PIC_EINVAL;
+  if (!(c->dz > 0) || !(c->dr > 0) || !(c->dt > 0) || !isfinite(c->z_min)) return PIC_EINVAL;
+  if (c->dt > 8.0 * c->dz || c->dt > 8.0 * c->dr) return PIC_EINVAL;
+  if (c->moving_window && fabs(c->dt - c->dz) > 1e-12 * c->dz) return PIC_EINVAL;
+  if (c->kperp_grid < 0 || c->kperp_grid > 2) return PIC_EINVAL;
+  if (c->hankel_prec < 0 || c->hankel_prec > 2) return PIC_EINVAL;
+  if (ns < 0 || ns > kMaxSpecies || (ns > 0 && !s)) return PIC_EINVAL;
+  for (int i = 0; i < ns; ++i) {
+    const pic_species& p = s[i];
+    if (p.n < 0 || !(p.m > 0) || p.q == 0.0 || !isfinite(p.q)) return PIC_EINVAL;
+    if (p.n > 0 && (!p.x || !p.y || !p.z || !p.w)) return PIC_EINVAL;
+    if (p.n > 0 && p.mobile && (!p.ux || !p.uy || !p.uz)) return PIC_EINVAL;
+    if (p.inject && (p.ppc_z < 1 || p.ppc_r < 1 || p.ppc_t < 1 || !(p.density > 0))) return PIC_EINVAL;
+  }
+  return PIC_OK;
+}
+
+struct Counts {
+  int64_t mobile = 0, immobile = 0, inject_per_step = 0;
+};
+
+Counts count_species(const pic_config* c, const pic_species* s, int ns) {
+  Counts k;
+  for (int i = 0; i < ns; ++i) {
+    if (s[i].mobile) k.mobile += s[i].n;
+    else k.immobile += s[i].n;
+    if (s[i].mobile && s[i].inject) k.inject_per_step += (int64_t)c->nr * s[i].ppc_z * s[i].ppc_r * s[i].ppc_t;
+  }
+  return k;
+}
+
+int64_t capacity_for(const pic_config* c, const pic_species* s, int ns, int64_t max_particles) {
+  Counts k = count_species(c, s, ns);
+  int64_t cap = max_particles > 0 ? max_particles : k.mobile + k.mobile / 8 + 2 * k.inject_per_step;
+  cap = std::max(cap, k.mobile + k.inject_per_step);
+  cap = std::max(cap, k.immobile);
+  cap = std::max<int64_t>(cap, 256);
+  return (cap + 255) / 256 * 256;
+}
+
+// Lays out (or measures) the workspace.
+int halo_cells(double dt, double d) { return std::max(1, (int)ceil(dt / d - 1e-12)); }
+
+size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
+  Carver cv;
+  const DepositShape dep = deposit_shape(c->nz, c->nr, c->n_modes, halo_cells(c->dt, c->dz),
+                                         halo_cells(c->dt, c->dr), cap);
+  cv.base = base;
+  const int M = c->n_modes, nz = c->nz, nr = c->nr;
+  const size_t plane = (size_t)nr * nz;
+  const int ncells = nz * (nr + 1);
+  DevState* st = cv.take<DevState>(1);
+  Parts pp[2];
+  for (int b = 0; b < 2; ++b) {
+    pp[b].x = cv.take<double>(cap);
+    pp[b].y = cv.take<double>(cap);
+    pp[b].z = cv.take<double>(cap);
+    pp[b].ux = cv.take<float>(cap);
+    pp[b].uy = cv.take<float>(cap);
+    pp[b].uz = cv.take<float>(cap);
+    pp[b].w = cv.take<float>(cap);
+    pp[b].sp = cv.take<uint8_t>(cap);
+  }
+  uint32_t* key = cv.take<uint32_t>(cap);
+  int* count = cv.take<int>(ncells + 2);
+  int* offset = cv.take<int>(ncells + 2);
+  int* cursor = cv.take<int>(ncells + 2);
+  int* bsum = cv.take<int>(scan_scratch_ints(ncells + 1));
+  int* dep_nchunk = cv.take<int>(dep.ntiles);
+  int* dep_start = cv.take<int>(dep.ntiles + 1);
+  float2* dep_partial = cv.take<float2>((size_t)dep.max_items * dep.acc_floats2);
+  float2* real = cv.take<float2>(kNumComp * M * plane);
+  float2* spec = cv.take<float2>(kNumComp * M * plane);
+  float2* tmp = cv.take<float2>(kNumComp * M * plane);
+  float2* bg = cv.take<float2>(M * plane);
+  float2* tail = cv.take<float2>(6 * M * nr);
+  float2* tailhat = cv.take<float2>(6 * M * nr);
+  double* kz = cv.take<double>(nz);
+  double* kzm = cv.take<double>(nz);
+  double* kperp = cv.take<double>(M * nr);
+  float2* tw = cv.take<float2>(nz);
+  float* mats = cv.take<float>((size_t)M * 6 * nr * nr);
+  double* setup64 = cv.take<double>((size_t)6 * nr * nr);
+  const float** ptr_tab = cv.take<const float*>((size_t)(3 * (5 + 6 + 6) + 6) * M);
+  double* dpart = cv.take<double>(diag_partial_doubles());
+  double* dout = cv.take<double>(32);
+  double* dsl = cv.take<double>(4 * kMaxSlices);
+  int* misc = cv.take<int>(16);
+  if (x) {
+    x->st = st;
+    x->parts[0] = pp[0];
+    x->parts[1] = pp[1];
+    x->key = key;
+    x->count = count;
+    x->offset = offset;
+    x->cursor = cursor;
+    x->bsum = bsum;
+    x->dep_nchunk = dep_nchunk;
+    x->dep_start = dep_start;
+    x->dep_partial = dep_partial;
+    x->dep = dep;
+    x->real = real;
+    x->spec = spec;
+    x->tmp = tmp;
+    x->bg = bg;
+    x->tail = tail;
+    x->tailhat = tailhat;
+    x->kz = kz;
+    x->kzm = kzm;
+    x->kperp = kperp;
+    x->tw = tw;
+    x->mats = mats;
+    x->setup64 = setup64;
+    x->ptr_tab = ptr_tab;
+    x->diag_partial = dpart;
+    x->diag_out = dout;
+    x->diag_slices = dsl;
+    x->misc = misc;
+  }
+  return cv.off + kAlign;
+}
+
+inline size_t plane_of(const pic_ctx* x) { return (size_t)x->nr * x->nz; }
+inline float2* fld(float2* base, const pic_ctx* x, int c, int m) {
+  return base + ((size_t)c * x->M + m) * plane_of(x);
+}
+// matrix slot of Hankel order nu in mode m: nu = m - 1, m, m + 1 -> 0, 1, 2
+inline float* mat(const pic_ctx* x, int m, int nu, int dir) {
+  int slot = nu - (m - 1);
+  return x->mats + ((size_t)(m * 3 + slot) * 2 + dir) * x->nr * x->nr;
+}
+inline int comp_nu(int c, int m) {
+  // E+,E-,Ez,B+,B-,Bz,J+,J-,Jz,rho,rho
+  static const int d[kNumComp] = {1, -1, 0, 1, -1, 0, 1, -1, 0, 0, 0};
+  return m + d[c];
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EHIP; }
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PIC_OK : PIC_EHIP;
+}
+
+int sync(pic_ctx* x) {
+  hipError_t e = hipStreamSynchronize(x->stream);
+  if (e != hipSuccess) return PIC_EHIP;
+  int rc = check_launch();
+  if (rc) return rc;
+  int ovf = 0;
+  if (hipMemcpy(&ovf, &x->st->overflow, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+  return ovf ? PIC_ENOSPC : PIC_OK;   // particle capacity or deposit work list exceeded
+}
+
+hipEvent_t take_event(pic_ctx* x) {
+  if (x->ev_used == x->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    x->ev_pool.push_back(e);
+  }
+  return x->ev_pool[x->ev_used++];
+}
+
+// brackets the enclosed launches with events when timing is on
+struct Phase {
+  pic_ctx* x;
+  int phase;
+  hipEvent_t a = nullptr;
+  Phase(pic_ctx* x_, int ph) : x(x_), phase(ph) {
+    if (x->timing) {
+      a = take_event(x);
+      if (a) (void)hipEventRecord(a, x->stream);
+    }
+  }
+  ~Phase() {
+    if (x->timing && a) {
+      hipEvent_t b = take_event(x);
+      if (b) {
+        (void)hipEventRecord(b, x->stream);
+        x->recs.push_back({phase, a, b});
+      }
+    }
+  }
+};
+
+// forward transform: real[c0 .. c0+nc) -> tmp (FFT) -> spec (DHT)
+void forward_transform(pic_ctx* x, float2* src_base, int c0, int nc, int pt_entry) {
+  const int M = x->M;
+  {
+    Phase ph(x, PIC_T_FFT_FWD);
+    launch_fft(fld(src_base, x, c0, 0), fld(x->tmp, x, c0, 0), x->tw, x->nz, (int64_t)nc * M * x->nr, false, false,
+               nullptr, x->stream);
+  }
+  const float* const* tab = x->ptr_tab + pt_entry;
+  int batch = nc * M;
+  Phase ph(x, PIC_T_DHT_FWD);
+  launch_dht_gemm(tab, tab + batch, (float* const*)(tab + 2 * batch), batch, x->nr, 2 * x->nz,
+                  x->cfg.hankel_prec, x->gemm_bm, x->stream);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// interface
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* pic_strerror(int status) {
+  switch (status) {
+    case PIC_OK: return "ok";
+    case PIC_EINVAL: return "invalid argument";
+    case PIC_ENOSPC: return "workspace too small or particle capacity exceeded";
+    case PIC_EHIP: return "HIP runtime error";
+    case PIC_ESTATE: return "call out of order";
+    case PIC_ENUMERIC: return "non-finite value detected";
+    default: return "unknown status";
+  }
+}
+
+int pic_workspace_bytes(const pic_config* cfg, const pic_species* species, int n_species, int64_t max_particles,
+                        size_t* bytes) {
+  if (!bytes) return PIC_EINVAL;
+  int v = validate(cfg, species, n_species);
+  if (v) return v;
+  int64_t cap = capacity_for(cfg, species, n_species, max_particles);
+  if (cap > (int64_t)INT32_MAX / 2) return PIC_EINVAL;
+  *bytes = carve(nullptr, nullptr, cfg, cap);
+  return PIC_OK;
+}
+
+int pic_init(const pic_config* cfg, const pic_species* species, int n_species, int64_t max_particles,
+             void* workspace, size_t bytes, void* hip_stream, pic_ctx** out) {
+  if (!out || !workspace) return PIC_EINVAL;
+  *out = nullptr;
+  int v = validate(cfg, species, n_species);
+  if (v) return v;
+  int64_t cap = capacity_for(cfg, species, n_species, max_particles);
+  if (cap > (int64_t)INT32_MAX / 2) return PIC_EINVAL;
+  size_t need = carve(nullptr, nullptr, cfg, cap);
+  if (bytes < need) return PIC_ENOSPC;
+  Counts cnt = count_species(cfg, species, n_species);
+  if (cnt.mobile > cap) return PIC_ENOSPC;
+
+  pic_ctx* x = new pic_ctx();   // value-initialized: every scalar member starts at zero
+  x->cfg = *cfg;
+  x->stream = (hipStream_t)hip_stream;
+  x->M = cfg->n_modes;
+  x->nz = cfg->nz;
+  x->nr = cfg->nr;
+  x->cap = cap;
+  x->n_species = n_species;
+  char* base = (char*)(((uintptr_t)workspace + kAlign - 1) / kAlign * kAlign);
+  carve(x, base, cfg, cap);
+  Grid& g = x->g;
+  g.nz = cfg->nz;
+  g.nr = cfg->nr;
+  g.nmodes = cfg->n_modes;
+  g.ncol = cfg->nr + 1;
+  g.ncells = cfg->nz * (cfg->nr + 1);
+  g.dz = cfg->dz;
+  g.dr = cfg->dr;
+  g.dt = cfg->dt;
+  g.inv_dz = 1.0 / cfg->dz;
+  g.inv_dr = 1.0 / cfg->dr;
+  g.zmin0 = cfg->z_min;
+  g.moving_window = cfg->moving_window;
+  x->hz = halo_cells(cfg->dt, cfg->dz);
+  x->hr = halo_cells(cfg->dt, cfg->dr);
+  x->gemm_bm = 2;
+  hipStream_t s = x->stream;
+  const int M = x->M, nr = x->nr, nz = x->nz;
+  const size_t plane = plane_of(x);
+
+  // species tables
+  x->inj.ns = 0;
+  x->inj.total = 0;
+  for (int i = 0; i < n_species; ++i) {
+    const pic_species& p = species[i];
+    SpeciesInfo& si = x->sp[i];
+    si.q = p.q;
+    si.m = p.m;
+    si.mobile = p.mobile;
+    si.inject = p.inject;
+    si.ppc_z = p.ppc_z;
+    si.ppc_r = p.ppc_r;
+    si.ppc_t = p.ppc_t;
+    si.diag = p.diag;
+    si.density = p.density;
+    si.n = p.n;
+    x->sc.qm[i] = (float)(p.q / p.m);
+    if (p.mobile && p.inject && cfg->moving_window) {
+      int k = x->inj.ns++;
+      x->inj.start[k] = x->inj.total;
+      x->inj.ppc_z[k] = p.ppc_z;
+      x->inj.ppc_r[k] = p.ppc_r;
+      x->inj.ppc_t[k] = p.ppc_t;
+      x->inj.sp[k] = i;
+      x->inj.q[k] = p.q;
+      x->inj.density[k] = p.density;
+      x->inj.total += nr * p.ppc_z * p.ppc_r * p.ppc_t;
+    }
+  }
+
+  int rc = PIC_OK;
+  // -------- zero everything that is read before written
+  launch_fill_zero(x->count, (size_t)(g.ncells + 2) * sizeof(int), s);
+  launch_fill_zero(x->real, kNumComp * M * plane * sizeof(float2), s);
+  launch_fill_zero(x->spec, kNumComp * M * plane * sizeof(float2), s);
+  launch_fill_zero(x->bg, M * plane * sizeof(float2), s);
+  launch_fill_zero(x->tailhat, 6 * M * nr * sizeof(float2), s);
+  launch_fill_zero(x->misc, 16 * sizeof(int), s);
+
+  // -------- FP64 spectral setup
+  launch_kz_table(x->kz, x->kzm, nz, cfg->dz, cfg->order, s);
+  launch_twiddles(x->tw, nz, s);
+  const double R = nr * cfg->dr;
+  for (int m = 0; m < M; ++m) launch_kperp(x->kperp + (size_t)m * nr, nr, R, cfg->kperp_grid, m, s);
+  for (int m = 0; m < M; ++m) {
+    double* B = x->setup64;                       // 3 synthesis matrices
+    double* F = x->setup64 + (size_t)3 * nr * nr; // 3 copies inverted in place
+    for (int slot = 0; slot < 3; ++slot) {
+      int nu = m - 1 + slot;
+      launch_bessel_matrix(B + (size_t)slot * nr * nr, x->kperp + (size_t)m * nr, nr, cfg->dr, nu, s);
+    }
+    PIC_CK(hipMemcpyAsync(F, B, (size_t)3 * nr * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_gauss_jordan(F, 3, nr, x->misc + 0, s);
+    for (int slot = 0; slot < 3; ++slot) {
+      int nu = m - 1 + slot;
+      launch_to_f32_transposed(F + (size_t)slot * nr * nr, mat(x, m, nu, 0), nr, s);
+      launch_to_f32_transposed(B + (size_t)slot * nr * nr, mat(x, m, nu, 1), nr, s);
+    }
+  }
+  // pointer tables for the batched products
+  {
+    std::vector<const float*> tab;
+    auto add_batch = [&](int c0, int nc, int dir, float2* xin, float2* yout) {
+      int start = (int)tab.size();
+      std::vector<const float*> a, xs, ys;
+      for (int c = c0; c < c0 + nc; ++c)
+        for (int m = 0; m < M; ++m) {
+          a.push_back(mat(x, m, comp_nu(c, m), dir));
+          xs.push_back((const float*)fld(xin, x, c, m));
+          ys.push_back((const float*)fld(yout, x, c, m));
+        }
+      tab.insert(tab.end(), a.begin(), a.end());
+      tab.insert(tab.end(), xs.begin(), xs.end());
+      tab.insert(tab.end(), ys.begin(), ys.end());
+      return start;
+    };
+    x->pt_fwd_src = add_batch(kCompJ, kNumSrc, 0, x->tmp, x->spec);
+    x->pt_fwd_eb = add_batch(0, 6, 0, x->tmp, x->spec);
+    x->pt_inv_eb = add_batch(0, 6, 1, x->spec, x->tmp);
+    // tail transform: F_nu of each E/B (c, m)
+    x->pt_tail = (int)tab.size();
+    for (int c = 0; c < 6; ++c)
+      for (int m = 0; m < M; ++m) tab.push_back(mat(x, m, comp_nu(c, m), 0));
+    PIC_CK(hipMemcpyAsync((void*)x->ptr_tab, tab.data(), tab.size() * sizeof(float*), hipMemcpyHostToDevice, s));
+    PIC_CK(hipStreamSynchronize(s));
+  }
+
+  // -------- immobile background: sort + deposit, transform once
+  x->have_bg = cnt.immobile > 0;
+  x->cur = 0;
+  if (x->have_bg) {
+    Parts& P = x->parts[1];
+    int64_t off = 0;
+    for (int i = 0; i < n_species; ++i) {
+      const pic_species& p = species[i];
+      if (p.mobile || p.n == 0) continue;
+      std::vector<float> qw(p.n);
+      for (int64_t k = 0; k < p.n; ++k) qw[k] = (float)(p.q * (double)p.w[k]);
+      PIC_CK(hipMemcpyAsync(P.x + off, p.x, p.n * sizeof(double), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.y + off, p.y, p.n * sizeof(double), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.z + off, p.z, p.n * sizeof(double), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.w + off, qw.data(), p.n * sizeof(float), hipMemcpyHostToDevice, s));
+      PIC_CK(hipStreamSynchronize(s));
+      off += p.n;
+    }
+    launch_fill_zero(P.ux, cap * sizeof(float), s);
+    launch_fill_zero(P.uy, cap * sizeof(float), s);
+    launch_fill_zero(P.uz, cap * sizeof(float), s);
+    launch_fill_zero(P.sp, cap, s);
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, x->st, cfg->z_min, (int)off);
+    launch_keys(P, g, x->st, x->key, x->count, (int)cap, s);
+    launch_scan(x->count, g.ncells + 1, x->bsum, x->offset, x->cursor, g.ncells, x->st, s);
+    launch_scatter(P, x->parts[0], x->key, x->cursor, x->st, g.ncells, (int)cap, s);
+    launch_deposit(x->parts[0], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real, nullptr, g,
+                   x->st, s);
+    if (cfg->moving_window) {
+      launch_uniform_check(fld(x->real, x, kCompJ + 4, 0), M * nr, nz, (unsigned*)(x->misc + 1), s);
+    }
+    // keep the real-space background density: every deposit adds it node by node
+    PIC_CK(hipMemcpyAsync(x->bg, fld(x->real, x, kCompJ + 4, 0), M * plane * sizeof(float2),
+                          hipMemcpyDeviceToDevice, s));
+    launch_fill_zero(x->real, kNumComp * M * plane * sizeof(float2), s);
+  }
+
+  // -------- mobile particles
+  {
+    Parts& P = x->parts[0];
+    int64_t off = 0;
+    for (int i = 0; i < n_species; ++i) {
+      const pic_species& p = species[i];
+      if (!p.mobile || p.n == 0) continue;
+      std::vector<float> qw(p.n);
+      std::vector<uint8_t> id(p.n, (uint8_t)i);
+      for (int64_t k = 0; k < p.n; ++k) qw[k] = (float)(p.q * (double)p.w[k]);
+      PIC_CK(hipMemcpyAsync(P.x + off, p.x, p.n * sizeof(double), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.y + off, p.y, p.n * sizeof(double), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.z + off, p.z, p.n * sizeof(double), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.ux + off, p.ux, p.n * sizeof(float), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.uy + off, p.uy, p.n * sizeof(float), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.uz + off, p.uz, p.n * sizeof(float), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.w + off, qw.data(), p.n * sizeof(float), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.sp + off, id.data(), p.n, hipMemcpyHostToDevice, s));
+      PIC_CK(hipStreamSynchronize(s));
+      off += p.n;
+    }
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, x->st, cfg->z_min, (int)off);
+  }
+  if (rc == PIC_OK) rc = sync(x);
+  if (rc == PIC_OK) {
+    int misc[3];
+    PIC_CK(hipMemcpy(misc, x->misc, sizeof(misc), hipMemcpyDeviceToHost));
+    if (misc[0]) rc = PIC_EINVAL;   // singular Hankel matrix
+    if (x->have_bg && cfg->moving_window) {
+      float dmax, amax;
+      memcpy(&dmax, &misc[1], 4);
+      memcpy(&amax, &misc[2], 4);
+      if (dmax > 1e-5f * amax) rc = PIC_EINVAL;   // background not uniform in z
+    }
+  }
+  if (rc != PIC_OK) {
+    delete x;
+    return rc;
+  }
+  x->phase = 0;
+  x->eb_stale = false;
+  x->spec_pending = false;
+  x->steps = 0;
+  x->n_shift = 0;
+  *out = x;
+  return PIC_OK;
+}
+
+int pic_gather_push(pic_ctx* x) {
+  if (!x) return PIC_EINVAL;
+  if (x->phase != 0) return PIC_ESTATE;
+  {
+    Phase ph(x, PIC_T_GATHER_PUSH);
+    launch_gather_push(x->parts[x->cur], x->real, x->g, x->sc, x->st, x->key, x->count, (int)x->cap, x->stream);
+  }
+  x->phase = 1;
+  return check_launch();
+}
+
+int pic_deposit(pic_ctx* x) {
+  if (!x) return PIC_EINVAL;
+  if (x->phase != 1) return PIC_ESTATE;
+  const Grid& g = x->g;
+  {
+    Phase ph(x, PIC_T_SORT);
+    launch_scan(x->count, g.ncells + 1, x->bsum, x->offset, x->cursor, g.ncells, x->st, x->stream);
+    launch_scatter(x->parts[x->cur], x->parts[x->cur ^ 1], x->key, x->cursor, x->st, g.ncells, (int)x->cap,
+                   x->stream);
+  }
+  x->cur ^= 1;
+  {
+    Phase ph(x, PIC_T_DEPOSIT);
+    launch_deposit(x->parts[x->cur], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real,
+                   x->have_bg ? x->bg : nullptr, g, x->st, x->stream);
+  }
+  x->phase = 2;
+  return check_launch();
+}
+
+int pic_spectral_push(pic_ctx* x) {
+  if (!x) return PIC_EINVAL;
+  bool sources_set = true;
+  for (int m = 0; m < x->M; ++m) sources_set = sources_set && (x->src_set[m] == 0x1Fu);
+  if (x->phase != 2 && !(x->phase == 0 && sources_set)) return PIC_ESTATE;
+  hipStream_t s = x->stream;
+  const int M = x->M, nr = x->nr, nz = x->nz;
+  bool apply_shift = x->spec_pending;
+  if (x->eb_stale) {
+    forward_transform(x, x->real, 0, 6, x->pt_fwd_eb);
+    x->eb_stale = false;
+    apply_shift = false;
+  }
+  forward_transform(x, x->real, kCompJ, kNumSrc, x->pt_fwd_src);
+  {
+    Phase ph(x, PIC_T_PSATD);
+    launch_psatd(x->spec, x->kperp, x->kzm, x->tw, x->tailhat, nz, nr, M, x->cfg.dt, apply_shift,
+                 x->cfg.current_correction != 0, s);
+  }
+  x->spec_pending = false;
+  {
+    Phase ph(x, PIC_T_DHT_INV);
+    const float* const* tab = x->ptr_tab + x->pt_inv_eb;
+    int batch = 6 * M;
+    launch_dht_gemm(tab, tab + batch, (float* const*)(tab + 2 * batch), batch, nr, 2 * nz, x->cfg.hankel_prec,
+                    x->gemm_bm, s);
+  }
+  const bool mw = x->cfg.moving_window != 0;
+  {
+    Phase ph(x, PIC_T_FFT_INV);
+    launch_fft(fld(x->tmp, x, 0, 0), fld(x->real, x, 0, 0), x->tw, nz, (int64_t)6 * M * nr, true, mw, x->tail, s);
+  }
+  if (mw) {
+    Phase ph(x, PIC_T_WINDOW);
+    launch_tail_transform(x->tail, x->tailhat, x->ptr_tab + x->pt_tail, nr, 6 * M, s);
+    hipLaunchKernelGGL(k_window_advance, dim3(1), dim3(1), 0, s, x->st, x->cfg.z_min, x->cfg.dz);
+    if (x->inj.total > 0) launch_inject(x->parts[x->cur], x->st, x->g, x->inj, (int)x->cap, s);
+    x->spec_pending = true;
+    x->n_shift += 1;
+  }
+  for (int m = 0; m < M; ++m) x->src_set[m] = 0;
+  x->phase = 0;
+  x->steps += 1;
+  return check_launch();
+}
+
+int pic_step(pic_ctx* x, int n) {
+  if (!x || n < 0) return PIC_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    int rc = pic_gather_push(x);
+    if (rc) return rc;
+    rc = pic_deposit(x);
+    if (rc) return rc;
+    rc = pic_spectral_push(x);
+    if (rc) return rc;
+  }
+  return PIC_OK;
+}
+
+int pic_sync(pic_ctx* x) {
+  if (!x) return PIC_EINVAL;
+  return sync(x);
+}
+
+int pic_num_particles(pic_ctx* x, int64_t* n) {
+  if (!x || !n) return PIC_EINVAL;
+  DiagSel sel{};
+  sel.kill = (x->cfg.moving_window && x->n_shift > 0) ? 1 : 0;
+  sel.zmin = x->cfg.z_min + (double)x->n_shift * x->cfg.dz;
+  int* counter = x->misc + 3;
+  launch_fill_zero(counter, sizeof(int), x->stream);
+  launch_count_alive(x->parts[x->cur], x->st, sel, counter, (int)x->cap, x->stream);
+  int rc = sync(x);
+  if (rc) return rc;
+  int v;
+  if (hipMemcpy(&v, counter, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+  *n = v;
+  return PIC_OK;
+}
+
+int pic_get_particles(pic_ctx* x, int species, int64_t cap, double* xyz, float* uvw, float* w, int64_t* n) {
+  if (!x || !xyz || !uvw || !n || species < 0 || species >= x->n_species || cap < 0) return PIC_EINVAL;
+  if (!x->sp[species].mobile) return PIC_EINVAL;
+  int rc = sync(x);
+  if (rc) return rc;
+  // stage through the ping-pong buffer that is not in use
+  const Parts& stage = x->parts[x->cur ^ 1];
+  int64_t lim = std::min<int64_t>(cap, x->cap);
+  DiagSel sel{};
+  sel.species = species;
+  sel.kill = (x->cfg.moving_window && x->n_shift > 0) ? 1 : 0;
+  sel.zmin = x->cfg.z_min + (double)x->n_shift * x->cfg.dz;
+  sel.inv_q = 1.0 / x->sp[species].q;
+  int* counter = x->misc + 3;
+  launch_fill_zero(counter, sizeof(int), x->stream);
+  launch_collect(x->parts[x->cur], x->st, sel, lim, stage, counter, (int)x->cap, x->stream);
+  rc = sync(x);
+  if (rc) return rc;
+  int cnt;
+  if (hipMemcpy(&cnt, counter, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+  int64_t got = std::min<int64_t>(cnt, lim);
+  std::vector<double> hx(got), hy(got), hz(got);
+  std::vector<float> hu(got), hv(got), hw(got), hq(got);
+  bool ok = hipMemcpy(hx.data(), stage.x, got * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(hy.data(), stage.y, got * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(hz.data(), stage.z, got * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(hu.data(), stage.ux, got * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(hv.data(), stage.uy, got * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(hw.data(), stage.uz, got * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(hq.data(), stage.w, got * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess;
+  if (!ok) return PIC_EHIP;
+  for (int64_t k = 0; k < got; ++k) {
+    xyz[3 * k] = hx[k];
+    xyz[3 * k + 1] = hy[k];
+    xyz[3 * k + 2] = hz[k];
+    uvw[3 * k] = hu[k];
+    uvw[3 * k + 1] = hv[k];
+    uvw[3 * k + 2] = hw[k];
+    if (w) w[k] = hq[k];
+  }
+  *n = got;
+  if (cnt > lim) return PIC_ENOSPC;
+  return PIC_OK;
+}
+
+int pic_get_field(pic_ctx* x, int mode, int comp, int spectral, void* host_dst) {
+  if (!x || !host_dst || mode < 0 || mode >= x->M || comp < 0 || comp >= kNumComp) return PIC_EINVAL;
+  if (spectral && comp < 6 && x->spec_pending) {
+    int64_t n = (int64_t)6 * x->M * plane_of(x);
+    hipLaunchKernelGGL(k_apply_shift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, x->stream, x->spec, x->tw,
+                       x->tailhat, x->nz, x->nr, x->M);
+    x->spec_pending = false;
+  }
+  int rc = sync(x);
+  if (rc) return rc;
+  const float2* src = fld(spectral ? x->spec : x->real, x, comp, mode);
+  if (hipMemcpy(host_dst, src, plane_of(x) * sizeof(float2), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+  return PIC_OK;
+}
+
+int pic_set_field(pic_ctx* x, int mode, int comp, const void* host_src) {
+  if (!x || !host_src || mode < 0 || mode >= x->M || comp < 0 || comp >= kNumComp) return PIC_EINVAL;
+  int rc = sync(x);
+  if (rc) return rc;
+  float2* dst = fld(x->real, x, comp, mode);
+  if (hipMemcpy(dst, host_src, plane_of(x) * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return PIC_EHIP;
+  if (comp < 6) {
+    x->eb_stale = true;
+    x->spec_pending = false;
+  } else {
+    x->src_set[mode] |= 1u << (comp - kCompJ);
+  }
+  return PIC_OK;
+}
+
+int pic_get_state(pic_ctx* x, double* z_min, int64_t* steps) {
+  if (!x) return PIC_EINVAL;
+  if (z_min) *z_min = x->cfg.z_min + (double)x->n_shift * x->cfg.dz;
+  if (steps) *steps = x->steps;
+  return PIC_OK;
+}
+
+int pic_diagnostics(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out) {
+  if (!x || !req || !out) return PIC_EINVAL;
+  if (req->species < 0 || req->species >= x->n_species || !x->sp[req->species].mobile) return PIC_EINVAL;
+  if (!(req->slice_len > 0) || !(req->n_sigma > 0)) return PIC_EINVAL;
+  memset(out, 0, sizeof(*out));
+  hipStream_t s = x->stream;
+  DiagSel sel{};
+  sel.species = req->species;
+  sel.kill = (x->cfg.moving_window && x->n_shift > 0) ? 1 : 0;
+  sel.zmin = x->cfg.z_min + (double)x->n_shift * x->cfg.dz;
+  sel.inv_q = 1.0 / x->sp[req->species].q;
+  const Parts& P = x->parts[x->cur];
+  launch_diag_pass1(P, x->st, sel, x->diag_partial, x->diag_out, s);
+  int rc = sync(x);
+  if (rc) return rc;
+  double a[9];
+  PIC_CK(hipMemcpy(a, x->diag_out, sizeof(a), hipMemcpyDeviceToHost));
+  if (rc) return rc;
+  out->n = (int64_t)a[0];
+  out->nan_flag = a[8] > 0 ? 1 : 0;
+  if (a[0] <= 0 || !(a[1] > 0)) return out->nan_flag ? PIC_ENUMERIC : PIC_OK;
+  const double W = a[1];
+  DiagMeans mu{};
+  mu.x = a[2] / W;
+  mu.y = a[3] / W;
+  mu.z = a[4] / W;
+  mu.ux = a[5] / W;
+  mu.uy = a[6] / W;
+  mu.g = a[7] / W;
+  launch_diag_pass2(P, x->st, sel, mu, x->diag_partial, x->diag_out, s);
+  rc = sync(x);
+  if (rc) return rc;
+  double b[8];
+  PIC_CK(hipMemcpy(b, x->diag_out, sizeof(b), hipMemcpyDeviceToHost));
+  if (rc) return rc;
+  for (double& v : b) v /= W;
+  out->eps_nx = sqrt(std::max(0.0, b[0] * b[1] - b[2] * b[2]));
+  out->eps_ny = sqrt(std::max(0.0, b[3] * b[4] - b[5] * b[5]));
+  out->mean_gamma = mu.g;
+  out->sigma_gamma = sqrt(b[6]);
+  out->z_mean = mu.z;
+  out->sigma_z = sqrt(b[7]);
+  if (out->sigma_z > 0) {
+    mu.slice_len = req->slice_len;
+    mu.zcut = req->n_sigma * out->sigma_z;
+    double h = ceil(mu.zcut / req->slice_len);
+    if (h > kMaxSlices / 2) return PIC_EINVAL;
+    mu.half = (int)h;
+    int ns = 2 * mu.half;
+    double* acc = x->diag_slices;
+    double* var = x->diag_slices + 3 * kMaxSlices;
+    launch_fill_zero(acc, 3 * (size_t)ns * sizeof(double), s);
+    launch_fill_zero(var, (size_t)ns * sizeof(double), s);
+    launch_diag_slices(P, x->st, sel, mu, acc, var, s);
+    rc = sync(x);
+    if (rc) return rc;
+    std::vector<double> ha(3 * (size_t)ns), hv(ns);
+    PIC_CK(hipMemcpy(ha.data(), acc, ha.size() * sizeof(double), hipMemcpyDeviceToHost));
+    PIC_CK(hipMemcpy(hv.data(), var, hv.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (rc) return rc;
+    double sum = 0;
+    int kept = 0;
+    for (int k = 0; k < ns; ++k) {
+      if (ha[3 * k] < req->min_per_slice || !(ha[3 * k + 1] > 0)) continue;
+      sum += sqrt(hv[k] / ha[3 * k + 1]);
+      ++kept;
+    }
+    out->n_slices = kept;
+    out->mean_slice_sigma_gamma = kept ? sum / kept : 0.0;
+  }
+  return out->nan_flag ? PIC_ENUMERIC : PIC_OK;
+}
+
+int pic_free(pic_ctx* x) {
+  if (!x) return PIC_EINVAL;
+  int rc = sync(x);
+  for (hipEvent_t e : x->ev_pool) (void)hipEventDestroy(e);
+  delete x;
+  return rc;
+}
+
+int pic_timing_enable(pic_ctx* x, int enable) {
+  if (!x) return PIC_EINVAL;
+  int rc = sync(x);
+  x->recs.clear();
+  x->ev_used = 0;
+  x->timing = enable != 0;
+  return rc;
+}
+
+int pic_timing_read(pic_ctx* x, int timer, double* total_ms, int64_t* launches) {
+  if (!x || timer < 0 || timer >= PIC_T_N || !total_ms || !launches) return PIC_EINVAL;
+  int rc = sync(x);
+  if (rc) return rc;
+  double t = 0.0;
+  int64_t k = 0;
+  for (const auto& r : x->recs) {
+    if (r.phase != timer) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return PIC_EHIP;
+    t += ms;
+    ++k;
+  }
+  *total_ms = t;
+  *launches = k;
+  return PIC_OK;
+}
+
+int pic_fft_z(void* data, int64_t rows, int nz, int inverse, void* hip_stream) {
+  if (!data || rows < 0 || !is_pow2(nz) || nz < 16 || nz > 4096) return PIC_EINVAL;
+  if (rows == 0) return PIC_OK;
+  launch_fft((float2*)data, (float2*)data, nullptr, nz, rows, inverse != 0, false, nullptr, (hipStream_t)hip_stream);
+  return check_launch();
+}
+
+int pic_dht_gemm(const void* const* a_t, const void* const* xin, void* const* y, int batch, int n, int ncols, int prec,
+                 void* hip_stream) {
+  if (!a_t || !xin || !y || batch < 0 || n < 32 || (n % 32) || ncols < 128 || (ncols % 128) || prec < 0 || prec > 2)
+    return PIC_EINVAL;
+  if (batch == 0) return PIC_OK;
+  launch_dht_gemm((const float* const*)a_t, (const float* const*)xin, (float* const*)y, batch, n, ncols, prec, 2,
+                  (hipStream_t)hip_stream);
+  return check_launch();
+}
+
+}  // extern "C"

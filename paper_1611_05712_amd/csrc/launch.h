@@ -1,0 +1,88 @@
+// Host-side launchers of the kernel translation units (all asynchronous on
+// the given stream).
+#pragma once
+
+#include "common.h"
+
+namespace pic {
+
+struct InjectTable {
+  int ns;                    // injecting mobile species
+  int total;                 // particles per window move (all species)
+  int start[kMaxSpecies];    // first injected index of each species
+  int ppc_z[kMaxSpecies], ppc_r[kMaxSpecies], ppc_t[kMaxSpecies];
+  int sp[kMaxSpecies];       // species id stored per particle
+  double q[kMaxSpecies], density[kMaxSpecies];
+};
+
+struct DiagSel {
+  int species;
+  int kill;
+  double inv_q;
+  double zmin;
+};
+
+struct DiagMeans {
+  double x, y, z, ux, uy, g;
+  double slice_len, zcut;
+  int half;
+};
+
+// setup (FP64)
+void launch_kz_table(double* kz, double* kzm, int nz, double dz, int order, hipStream_t st);
+void launch_kperp(double* kperp, int nr, double R, int kind, int m, hipStream_t st);
+void launch_bessel_matrix(double* B, const double* kperp, int nr, double dr, int nu, hipStream_t st);
+void launch_gauss_jordan(double* A, int count, int n, int* fail, hipStream_t st);
+void launch_to_f32_transposed(const double* in, float* out, int n, hipStream_t st);
+void launch_twiddles(float2* tw, int n, hipStream_t st);
+
+// particles
+void launch_gather_push(const Parts& p, const float2* real, const Grid& g, const SpeciesConst& sc,
+                        const DevState* st, uint32_t* key, int* count, int cap, hipStream_t s);
+void launch_keys(const Parts& p, const Grid& g, const DevState* st, uint32_t* key, int* count, int cap,
+                 hipStream_t s);
+int scan_scratch_ints(int n);
+void launch_scan(int* count, int n, int* bsum, int* offset, int* cursor, int ncells, DevState* st, hipStream_t s);
+void launch_scatter(const Parts& src, const Parts& dst, const uint32_t* key, int* cursor, const DevState* st,
+                    int ncells, int cap, hipStream_t s);
+struct DepositShape {
+  int TZ, TR, ntz, ntr, ntiles;
+  int max_items;        // workgroups launched (upper bound of the work list)
+  size_t acc_floats2;   // complex accumulators per tile
+  int hz, hr;
+};
+DepositShape deposit_shape(int nz, int nr, int nmodes, int hz, int hr, int64_t cap);
+void launch_deposit(const Parts& p, const int* offset, const DepositShape& d, int* nchunk, int* chunk_start,
+                    float2* partial, float2* real, const float2* bg, const Grid& g, DevState* st, hipStream_t s);
+void launch_inject(const Parts& p, DevState* st, const Grid& g, const InjectTable& tab, int cap, hipStream_t s);
+void launch_uniform_check(const float2* rho, int rows, int nz, unsigned int* out, hipStream_t s);
+
+// fields
+void fft_config(int nz, int& rows_per_wg, size_t& lds);
+void launch_fft(const float2* in, float2* out, const float2* tw, int nz, int64_t rows, bool inverse, bool shift,
+                float2* tail, hipStream_t s);
+int gemm_tile_bm(int n, int pref_bm);
+void launch_dht_gemm(const float* const* at, const float* const* x, float* const* y, int batch, int n, int ncols,
+                     int prec, int pref_bm, hipStream_t s);
+void launch_psatd(float2* spec, const double* kperp, const double* kzm, const float2* tw, const float2* tailhat,
+                  int nz, int nr, int M, double dt, bool apply_shift, bool correct, hipStream_t s);
+void launch_tail_transform(const float2* tail, float2* tailhat, const float* const* ft_of_row, int nr, int nrows,
+                           hipStream_t s);
+
+// diagnostics
+int diag_partial_doubles();
+void launch_diag_pass1(const Parts& p, const DevState* st, const DiagSel& sel, double* partial, double* out,
+                       hipStream_t s);
+void launch_diag_pass2(const Parts& p, const DevState* st, const DiagSel& sel, const DiagMeans& mu, double* partial,
+                       double* out, hipStream_t s);
+void launch_diag_slices(const Parts& p, const DevState* st, const DiagSel& sel, const DiagMeans& mu, double* acc,
+                        double* var, hipStream_t s);
+void launch_collect(const Parts& p, const DevState* st, const DiagSel& sel, int64_t cap, const Parts& out,
+                    int* counter, int nmax, hipStream_t s);
+void launch_count_alive(const Parts& p, const DevState* st, const DiagSel& sel, int* counter, int nmax,
+                        hipStream_t s);
+
+// small utilities (api.hip)
+void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace pic

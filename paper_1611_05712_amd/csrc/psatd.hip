@@ -1,0 +1,155 @@
+// Spectral step: pending window shift, current correction and the order-p
+// PSATD update, fused per spectral cell (k_perp, k_z) and looped over modes.
+//
+// In plasma units (c = 1) the paper's Eqs. (1a)-(1b) with the quasi-cylindrical
+// operators of Eqs. (2a)-(2b) read, with k = sqrt(k_perp^2 + [k_z]^2),
+// C = cos(k dt), S = sin(k dt):
+//   E' = C E + (S/k) curl B - (S/k) J
+//        + grad[((S/(k dt) - 1) rho^{n+1} + (C - S/(k dt)) rho^n) / k^2]
+//   B' = C B - (S/k) curl E + ((1 - C)/k^2) curl J
+//   grad s    = (-k_perp s/2, +k_perp s/2, i [k_z] s)
+//   curl V    = ([k_z] V+ - i k_perp Vz/2, -[k_z] V- - i k_perp Vz/2, i k_perp (V+ + V-))
+//   div V     = k_perp (V+ - V-) + i [k_z] Vz
+// Current correction: J += grad F, F = (div J + (rho^{n+1} - rho^n)/dt) / k^2.
+// The coefficients are evaluated in FP64 (C, S, and the cancellation-prone
+// S/(k dt) - 1 near k -> 0) and rounded once to float32.
+//
+// A moving window shifts the real-space fields one cell toward the tail and
+// zeroes the head column.  On the spectral state that is
+//   F <- exp(+i k_z dz) (F - F_nu c)
+// with c the real-space column that left the window; it is applied here,
+// before the update, so the spectral E, B never round-trip through real space.
+#include "common.h"
+#include "launch.h"
+
+namespace pic {
+
+struct Coef {
+  float C, Sk, omc, r1, r0, ik2;
+};
+
+__device__ __forceinline__ Coef make_coef(double kp, double kz, double dt) {
+  double k2 = kp * kp + kz * kz;
+  double k = sqrt(k2);
+  double x = k * dt;
+  double s, c;
+  sincos(x, &s, &c);
+  double sx = s / x;
+  Coef o;
+  o.C = (float)c;
+  o.Sk = (float)(s / k);
+  o.omc = (float)((1.0 - c) / k2);
+  o.r1 = (float)((sx - 1.0) / k2);
+  o.r0 = (float)((c - sx) / k2);
+  o.ik2 = (float)(1.0 / k2);
+  return o;
+}
+
+__global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const double* __restrict__ kperp,
+                                               const double* __restrict__ kzm, const float2* __restrict__ tw,
+                                               const float2* __restrict__ tailhat, int nz, int nr, int M, double dt,
+                                               int apply_shift, int correct) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= (int64_t)nr * nz) return;
+  const int ik = (int)(cell / nz);
+  const int iz = (int)(cell % nz);
+  const double kzd = kzm[iz];
+  const float kz = (float)kzd;
+  const size_t plane = (size_t)nr * nz;
+  float2 ph = make_float2(1.f, 0.f);
+  if (apply_shift) ph = cconj(tw[iz]);   // exp(+2 pi i iz / nz)
+  double kp_prev = -1.0;
+  Coef co{};
+  for (int m = 0; m < M; ++m) {
+    const double kpd = kperp[m * nr + ik];
+    if (kpd != kp_prev) {
+      co = make_coef(kpd, kzd, dt);
+      kp_prev = kpd;
+    }
+    const float kp = (float)kpd;
+    float2* f[kNumComp];
+#pragma unroll
+    for (int c = 0; c < kNumComp; ++c) f[c] = spec + ((size_t)c * M + m) * plane + cell;
+    float2 E[3], B[3], J[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      E[c] = *f[c];
+      B[c] = *f[3 + c];
+      J[c] = *f[6 + c];
+    }
+    float2 r0 = *f[9], r1 = *f[10];
+    if (apply_shift) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        E[c] = cmul(ph, csub(E[c], tailhat[((size_t)c * M + m) * nr + ik]));
+        B[c] = cmul(ph, csub(B[c], tailhat[((size_t)(3 + c) * M + m) * nr + ik]));
+      }
+    }
+    const float idt = (float)(1.0 / dt);
+    if (correct) {
+      float2 dvj = cadd(cscale(csub(J[0], J[1]), kp), cmuli(cscale(J[2], kz)));
+      float2 F = cscale(cadd(dvj, cscale(csub(r1, r0), idt)), co.ik2);
+      J[0] = cadd(J[0], cscale(F, -0.5f * kp));
+      J[1] = cadd(J[1], cscale(F, 0.5f * kp));
+      J[2] = cadd(J[2], cmuli(cscale(F, kz)));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) *f[6 + c] = J[c];
+    }
+    // curls
+    float2 cB[3], cE[3], cJ[3];
+    {
+      const float hk = 0.5f * kp;
+      cB[0] = csub(cscale(B[0], kz), cmuli(cscale(B[2], hk)));
+      cB[1] = csub(cscale(B[1], -kz), cmuli(cscale(B[2], hk)));
+      cB[2] = cmuli(cscale(cadd(B[0], B[1]), kp));
+      cE[0] = csub(cscale(E[0], kz), cmuli(cscale(E[2], hk)));
+      cE[1] = csub(cscale(E[1], -kz), cmuli(cscale(E[2], hk)));
+      cE[2] = cmuli(cscale(cadd(E[0], E[1]), kp));
+      cJ[0] = csub(cscale(J[0], kz), cmuli(cscale(J[2], hk)));
+      cJ[1] = csub(cscale(J[1], -kz), cmuli(cscale(J[2], hk)));
+      cJ[2] = cmuli(cscale(cadd(J[0], J[1]), kp));
+    }
+    const float2 gs = cadd(cscale(r1, co.r1), cscale(r0, co.r0));
+    const float2 g[3] = {cscale(gs, -0.5f * kp), cscale(gs, 0.5f * kp), cmuli(cscale(gs, kz))};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float2 En = cadd(cadd(cscale(E[c], co.C), cscale(csub(cB[c], J[c]), co.Sk)), g[c]);
+      float2 Bn = cadd(csub(cscale(B[c], co.C), cscale(cE[c], co.Sk)), cscale(cJ[c], co.omc));
+      *f[c] = En;
+      *f[3 + c] = Bn;
+    }
+  }
+}
+
+// tailhat[c][m][k] = sum_r F_nu[k][r] tail[c][m][r]  (F stored transposed: ft[r][k])
+__global__ __launch_bounds__(256) void k_tail_transform(const float2* __restrict__ tail, float2* __restrict__ tailhat,
+                                                        const float* const* __restrict__ ft_of_row, int nr, int nrows) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // over nrows * nr (row = c*M + m)
+  if (idx >= nrows * nr) return;
+  const int row = idx / nr, k = idx % nr;
+  const float* ft = ft_of_row[row];
+  const float2* t = tail + (size_t)row * nr;
+  float sx = 0.f, sy = 0.f;
+  for (int r = 0; r < nr; ++r) {
+    float a = ft[(size_t)r * nr + k];
+    float2 v = t[r];
+    sx += a * v.x;
+    sy += a * v.y;
+  }
+  tailhat[idx] = make_float2(sx, sy);
+}
+
+void launch_psatd(float2* spec, const double* kperp, const double* kzm, const float2* tw, const float2* tailhat,
+                  int nz, int nr, int M, double dt, bool apply_shift, bool correct, hipStream_t s) {
+  int64_t n = (int64_t)nr * nz;
+  hipLaunchKernelGGL(k_psatd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spec, kperp, kzm, tw, tailhat, nz,
+                     nr, M, dt, apply_shift ? 1 : 0, correct ? 1 : 0);
+}
+
+void launch_tail_transform(const float2* tail, float2* tailhat, const float* const* ft_of_row, int nr, int nrows,
+                           hipStream_t s) {
+  int n = nrows * nr;
+  hipLaunchKernelGGL(k_tail_transform, dim3((n + 255) / 256), dim3(256), 0, s, tail, tailhat, ft_of_row, nr, nrows);
+}
+
+}  // namespace pic

@@ -1,0 +1,263 @@
+"""GPU parity of each stage of the PIC cycle (through the C interface) against
+the FP64 oracle on identical seeded inputs."""
+import numpy as np
+import pytest
+
+from oracle.cycle import OracleSim
+from oracle.diag import beam_moments
+from workloads import (KPERP_J0_ZEROS, Species, Workload, preset, random_particles,
+                       random_spectral)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FIELD_TOL = 1e-5      # relative L2 per (mode, component), FP32 fields after one step
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _sim(wl, **kw):
+    from paper_1611_05712_amd import Simulation
+    return Simulation.from_workload(wl, **kw)
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _random_fields(wl, seed, smooth=True):
+    """complex64-representable fields [M][comp][nr][nz]"""
+    f = random_spectral((wl.n_modes, 11, wl.nr, wl.nz), seed)
+    if smooth:
+        # damp the highest z and r frequencies (fields of a real run are smooth)
+        fz = np.fft.fft(f, axis=-1)
+        kz = np.fft.fftfreq(wl.nz)
+        fz *= np.exp(-(kz / 0.15) ** 2)
+        f = np.fft.ifft(fz, axis=-1)
+        ker = np.array([0.25, 0.5, 0.25])
+        f = np.apply_along_axis(lambda v: np.convolve(v, ker, mode="same"), -2, f)
+    return f.astype(np.complex64).astype(np.complex128)
+
+
+def _vacuum(nz=128, nr=64, order=16, moving=False, dt=None):
+    dz = 0.05
+    return Workload("vac", nz, nr, 2, order, dz, 0.05, dz if dt is None else dt, 0.0, moving,
+                    KPERP_J0_ZEROS, 1, [])
+
+
+COMPS = ["E+", "E-", "Ez", "B+", "B-", "Bz"]
+
+
+@pytest.mark.parametrize("order", [0, 16, 32])
+@pytest.mark.parametrize("nz,nr", [(128, 64), (256, 96)])
+def test_spectral_push_matches_oracle(order, nz, nr):
+    wl = _vacuum(nz, nr, order)
+    F = _random_fields(wl, seed=order + nz)
+    sim = _sim(wl)
+    for m in range(2):
+        for c in range(11):
+            sim.set_field(m, c, F[m, c])
+    sim.spectral_push()
+    o = OracleSim(wl)
+    o.E[:] = F[:, 0:3]
+    o.B[:] = F[:, 3:6]
+    o.J = F[:, 6:9].copy()
+    o.rho_old = F[:, 9].copy()
+    o.rho_new = F[:, 10].copy()
+    o.spectral_push()
+    worst = 0.0
+    for m in range(2):
+        for c, name in enumerate(COMPS):
+            want = (o.E if c < 3 else o.B)[m, c % 3]
+            worst = max(worst, _rel(sim.get_field(m, name), want))
+    assert worst < FIELD_TOL, worst
+
+
+def test_spectral_push_window_shift_two_steps():
+    # moving window: the second step applies the shift to the spectral state
+    # (phase ramp minus the departed column) instead of re-transforming
+    wl = _vacuum(128, 64, 16, moving=True)
+    F1 = _random_fields(wl, seed=11)
+    F2 = _random_fields(wl, seed=12)
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    for m in range(2):
+        for c in range(11):
+            sim.set_field(m, c, F1[m, c])
+    o.E[:] = F1[:, 0:3]
+    o.B[:] = F1[:, 3:6]
+    for F in (F1, F2):
+        for m in range(2):
+            for c in range(6, 11):
+                sim.set_field(m, c, F[m, c])
+        sim.spectral_push()
+        o.J, o.rho_old, o.rho_new = F[:, 6:9].copy(), F[:, 9].copy(), F[:, 10].copy()
+        o.spectral_push()
+    z, steps = sim.state()
+    assert steps == 2 and z == pytest.approx(2 * wl.dz)
+    for m in range(2):
+        for c, name in enumerate(COMPS):
+            want = (o.E if c < 3 else o.B)[m, c % 3]
+            assert _rel(sim.get_field(m, name), want) < 3 * FIELD_TOL, (m, name)
+
+
+def _species_from(p, name="p", q=-1.0, mass=1.0):
+    return Species(name, q, mass, True, p["x"], p["y"], p["z"], p["ux"], p["uy"], p["uz"], p["w"],
+                   diag=True)
+
+
+@pytest.mark.parametrize("n", [1, 37, 5000])
+def test_deposit_matches_oracle(n):
+    wl = _vacuum(128, 64, 16)
+    p = random_particles(n, wl.nz, wl.nr, wl.dz, wl.dr, wl.zmin, seed=n, u_scale=2.0)
+    wl.species = [_species_from(p)]
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.gather_push()
+    sim.deposit()
+    o.gather_push()
+    o.deposit()
+    names = ["J+", "J-", "Jz", "rho_old", "rho_new"]
+    want = {"J+": o.J[:, 0], "J-": o.J[:, 1], "Jz": o.J[:, 2], "rho_old": o.rho_old,
+            "rho_new": o.rho_new}
+    for m in range(2):
+        for name in names:
+            got = sim.get_field(m, name)
+            w = want[name][m]
+            scale = max(np.abs(w).max(), 1e-30)
+            assert np.abs(got - w).max() < 2e-6 * scale, (m, name)
+
+
+@pytest.mark.parametrize("kind", ["cluster", "axis"])
+def test_deposit_dense_clusters_match_oracle(kind):
+    # tens of thousands of particles in a few cells: long same-cell runs in
+    # every wavefront and tiles split over several workgroups (partial tiles
+    # combined), next to a sparse random background
+    wl = _vacuum(128, 64, 16)
+    rng = np.random.default_rng(17)
+    n = 70000
+    if kind == "cluster":
+        x = rng.normal(1.0, 0.01, n)
+        y = rng.normal(0.5, 0.01, n)
+    else:   # on the axis, where the ghost-node parity applies
+        x = rng.normal(0.0, 0.01, n)
+        y = rng.normal(0.0, 0.01, n)
+    z = rng.normal(3.2, 0.015, n)
+    u = (0.3 * rng.standard_normal((3, n))).astype(np.float32)
+    u[2] += 40.0
+    bgp = random_particles(2000, wl.nz, wl.nr, wl.dz, wl.dr, wl.zmin, seed=3, u_scale=1.0)
+    p = {"x": np.concatenate([x, bgp["x"]]), "y": np.concatenate([y, bgp["y"]]),
+         "z": np.concatenate([z, bgp["z"]]), "ux": np.concatenate([u[0], bgp["ux"]]),
+         "uy": np.concatenate([u[1], bgp["uy"]]), "uz": np.concatenate([u[2], bgp["uz"]]),
+         "w": np.concatenate([np.full(n, 1e-3, np.float32), bgp["w"]])}
+    wl.species = [_species_from(p)]
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.gather_push()
+    sim.deposit()
+    o.gather_push()
+    o.deposit()
+    want = {"J+": o.J[:, 0], "J-": o.J[:, 1], "Jz": o.J[:, 2], "rho_old": o.rho_old,
+            "rho_new": o.rho_new}
+    for m in range(2):
+        for name, w in want.items():
+            got = sim.get_field(m, name)
+            scale = max(np.abs(w[m]).max(), 1e-30)
+            assert np.abs(got - w[m]).max() < 5e-5 * scale, (m, name)
+
+
+def test_gather_push_matches_oracle():
+    wl = _vacuum(128, 64, 16)
+    p = random_particles(3001, wl.nz, wl.nr, wl.dz, wl.dr, wl.zmin, seed=5, u_scale=3.0)
+    wl.species = [_species_from(p)]
+    F = _random_fields(wl, seed=21)
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    for m in range(2):
+        for c in range(6):
+            sim.set_field(m, c, F[m, c])
+    o.E[:] = F[:, 0:3]
+    o.B[:] = F[:, 3:6]
+    sim.gather_push()
+    o.gather_push()
+    g = sim.get_particles(0)
+    s = o.species[0]
+    assert g["x"].size == s.x.size
+    ig = np.argsort(g["z"])
+    io = np.argsort(s.z)
+    for a, b in (("ux", s.ux), ("uy", s.uy), ("uz", s.uz)):
+        np.testing.assert_allclose(g[a][ig], b[io], rtol=2e-5, atol=2e-5 * np.abs(b).max())
+    for a, b in (("x", s.x), ("y", s.y), ("z", s.z)):
+        np.testing.assert_allclose(g[a][ig], b[io], rtol=0, atol=1e-7)
+
+
+def test_call_order_enforced():
+    from paper_1611_05712_amd import PicError
+    wl = preset("tiny")
+    sim = _sim(wl)
+    with pytest.raises(PicError) as e:
+        sim.deposit()
+    assert e.value.code == -4
+    with pytest.raises(PicError):
+        sim.spectral_push()
+    sim.gather_push()
+    with pytest.raises(PicError):
+        sim.gather_push()
+    sim.deposit()
+    sim.spectral_push()
+
+
+def test_diagnostics_match_oracle_on_initial_beam():
+    wl = preset("small")
+    sim = _sim(wl)
+    s = [x for x in wl.species if x.name == "drive"][0]
+    got = sim.diagnostics("drive", slice_len=0.02975)
+    want = beam_moments(s.x, s.y, s.z, s.ux, s.uy, s.uz, s.w, slice_len=0.02975)
+    for k in ("z_mean", "sigma_z", "mean_gamma"):
+        assert got[k] == pytest.approx(want[k], rel=1e-12)
+    for k in ("eps_nx", "eps_ny", "sigma_gamma", "mean_slice_sigma_gamma"):
+        assert got[k] == pytest.approx(want[k], rel=1e-6, abs=1e-12)
+    assert got["n_slices"] == want["n_slices"] and got["n"] == want["n"]
+
+
+@pytest.mark.parametrize("name", ["tiny", "small"])
+def test_full_cycle_one_step_fields(name):
+    wl = preset(name)
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.step(1)
+    o.step(1)
+    for m in range(2):
+        for c, cn in enumerate(COMPS):
+            want = (o.E if c < 3 else o.B)[m, c % 3]
+            if np.abs(want).max() < 1e-12:
+                continue
+            assert _rel(sim.get_field(m, cn), want) < FIELD_TOL, (m, cn)
+
+
+def test_full_cycle_small_ten_steps_beam_moments():
+    wl = preset("small")
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.step(10)
+    o.step(10)
+    s = o.species_by_name("drive")
+    want = beam_moments(s.x, s.y, s.z, s.ux, s.uy, s.uz, s.w, slice_len=0.02975)
+    got = sim.diagnostics("drive", slice_len=0.02975)
+    assert got["n"] == want["n"]
+    # near-zero quantities of a cold beam get an absolute floor of 1e-4 times
+    # the natural scale (sigma_x sigma_ux for emittances, gamma for sigma_gamma)
+    w = s.w / s.w.sum()
+    sx = np.sqrt((w * (s.x - (w * s.x).sum()) ** 2).sum())
+    sux = np.sqrt((w * (s.ux - (w * s.ux).sum()) ** 2).sum())
+    sy = np.sqrt((w * (s.y - (w * s.y).sum()) ** 2).sum())
+    suy = np.sqrt((w * (s.uy - (w * s.uy).sum()) ** 2).sum())
+    floors = {"eps_nx": sx * sux, "eps_ny": sy * suy, "sigma_gamma": want["mean_gamma"] * 1e-3}
+    for k in ("z_mean", "sigma_z", "mean_gamma", "sigma_gamma", "eps_nx", "eps_ny"):
+        assert got[k] == pytest.approx(want[k], rel=1e-4, abs=1e-4 * floors.get(k, 0.0)), k
+    assert sim.num_particles() == sum(x.x.size for x in o.species if x.mobile)

@@ -171,7 +171,7 @@ def preset(name: str, seed: int = 0) -> Workload:
                 100 pC drive bunch (gamma 1000, sigma 0.5), 50 steps.
     * ``c1``    2048 x 256 cells, 2 modes, p = 32, dz = 0.02, dr = 0.05, 1 nC drive
                 (1e6 particles) + 50 pC witness (2e5 particles), gamma 2000.
-    * ``tiny``  32 x 16 cells, 2 modes, p = 8, a 64-particle bunch: test-sized.
+    * ``tiny``  64 x 32 cells, 2 modes, p = 8, a 64-particle bunch: test-sized.
     * ``small`` 128 x 32 cells, 2 modes, p = 16, plasma + bunch: several tiles,
                 ragged particle counts; the oracle finishes in seconds.
     """
@@ -194,9 +194,9 @@ def preset(name: str, seed: int = 0) -> Workload:
         return Workload("c1", nz, nr, 2, 32, dz, dr, dz, zmin, True, KPERP_J0_ZEROS, 2000,
                         [ele, ion, drive, wit])
     if name == "tiny":
-        nz, nr, dz, dr = 32, 16, 0.1, 0.1
+        nz, nr, dz, dr = 64, 32, 0.1, 0.1
         zmin = 0.0
-        b = _bunch_species("bunch", 64, 20e-12, 50.0, 0.3, 0.4, 1.6, seed, True)
+        b = _bunch_species("bunch", 64, 20e-12, 50.0, 0.3, 0.4, 3.2, seed, True)
         return Workload("tiny", nz, nr, 2, 8, dz, dr, dz, zmin, False, KPERP_J0_ZEROS, 4, [b])
     if name == "small":
         nz, nr, dz, dr = 128, 32, 0.05, 0.05
