@@ -88,7 +88,7 @@ typedef struct {
   int32_t nr;          /* radial cells: multiple of 32, 32 <= nr <= 1024 */
   int32_t n_modes;     /* azimuthal modes m = 0..n_modes-1, 1 <= n_modes <= 4 */
   int32_t order;       /* stencil order p = 2n (even, >= 2); 0 = infinite order */
-  double dz, dr, dt;   /* > 0 */
+  double dz, dr, dt;   /* > 0; dt <= 2 min(dz, dr) (particles cross at most two cells per step) */
   double z_min;        /* position of node j = 0 at step 0 */
   int32_t moving_window;      /* 1: z_min advances by dz after every step (needs dt == dz) */
   int32_t kperp_grid;         /* pic_kperp_grid */

@@ -97,7 +97,8 @@ struct pic_ctx {
   int *count, *offset, *cursor, *bsum;
   int *dep_nchunk, *dep_start;
   float2* dep_partial;
-  float2 *real, *spec, *tmp, *bg, *tail, *tailhat;   // bg: real-space immobile density [m][r][z]
+  float2 *real, *spec, *tmp, *bg, *tail, *tailhat;
+  float2* gfield;        // node-interleaved real-space E, B for the gather: [r][z][m][6]   // bg: real-space immobile density [m][r][z]
   double *kz, *kzm, *kperp;
   float2* tw;
   float* mats;           // [m][order slot 0..2][dir 0 fwd / 1 bwd][nr][nr], transposed
@@ -149,7 +150,7 @@ int validate(const pic_config* c, const pic_species* s, int ns) {
   if (c->n_modes < 1 || c->n_modes > kMaxModes) return PIC_EINVAL;
   if (c->order < 0 || (c->order % 2) || c->order == 1) return PIC_EINVAL;
   if (!(c->dz > 0) || !(c->dr > 0) || !(c->dt > 0) || !isfinite(c->z_min)) return PIC_EINVAL;
-  if (c->dt > 8.0 * c->dz || c->dt > 8.0 * c->dr) return PIC_EINVAL;
+  if (c->dt > 2.0 * c->dz || c->dt > 2.0 * c->dr) return PIC_EINVAL;   // deposit halo of <= 2 cells
   if (c->moving_window && fabs(c->dt - c->dz) > 1e-12 * c->dz) return PIC_EINVAL;
   if (c->kperp_grid < 0 || c->kperp_grid > 2) return PIC_EINVAL;
   if (c->hankel_prec < 0 || c->hankel_prec > 2) return PIC_EINVAL;
@@ -192,8 +193,8 @@ int halo_cells(double dt, double d) { return std::max(1, (int)ceil(dt / d - 1e-1
 
 size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
   Carver cv;
-  const DepositShape dep = deposit_shape(c->nz, c->nr, c->n_modes, halo_cells(c->dt, c->dz),
-                                         halo_cells(c->dt, c->dr), cap);
+  const DepositShape dep = deposit_shape(c->nz, c->nr, c->n_modes,
+                                         std::max(halo_cells(c->dt, c->dz), halo_cells(c->dt, c->dr)), cap);
   cv.base = base;
   const int M = c->n_modes, nz = c->nz, nr = c->nr;
   const size_t plane = (size_t)nr * nz;
@@ -222,6 +223,7 @@ size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
   float2* spec = cv.take<float2>(kNumComp * M * plane);
   float2* tmp = cv.take<float2>(kNumComp * M * plane);
   float2* bg = cv.take<float2>(M * plane);
+  float2* gfield = cv.take<float2>(6 * M * plane);
   float2* tail = cv.take<float2>(6 * M * nr);
   float2* tailhat = cv.take<float2>(6 * M * nr);
   double* kz = cv.take<double>(nz);
@@ -253,6 +255,7 @@ size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
     x->tmp = tmp;
     x->bg = bg;
     x->tail = tail;
+    x->gfield = gfield;
     x->tailhat = tailhat;
     x->kz = kz;
     x->kzm = kzm;
@@ -456,6 +459,7 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
   launch_fill_zero(x->real, kNumComp * M * plane * sizeof(float2), s);
   launch_fill_zero(x->spec, kNumComp * M * plane * sizeof(float2), s);
   launch_fill_zero(x->bg, M * plane * sizeof(float2), s);
+  launch_fill_zero(x->gfield, 6 * M * plane * sizeof(float2), s);
   launch_fill_zero(x->tailhat, 6 * M * nr * sizeof(float2), s);
   launch_fill_zero(x->misc, 16 * sizeof(int), s);
 
@@ -597,7 +601,7 @@ int pic_gather_push(pic_ctx* x) {
   if (x->phase != 0) return PIC_ESTATE;
   {
     Phase ph(x, PIC_T_GATHER_PUSH);
-    launch_gather_push(x->parts[x->cur], x->real, x->g, x->sc, x->st, x->key, x->count, (int)x->cap, x->stream);
+    launch_gather_push(x->parts[x->cur], x->gfield, x->g, x->sc, x->st, x->key, x->count, (int)x->cap, x->stream);
   }
   x->phase = 1;
   return check_launch();
@@ -654,6 +658,7 @@ int pic_spectral_push(pic_ctx* x) {
   {
     Phase ph(x, PIC_T_FFT_INV);
     launch_fft(fld(x->tmp, x, 0, 0), fld(x->real, x, 0, 0), x->tw, nz, (int64_t)6 * M * nr, true, mw, x->tail, s);
+    launch_pack_gather(x->real, x->gfield, nr, nz, M, s);
   }
   if (mw) {
     Phase ph(x, PIC_T_WINDOW);
@@ -772,6 +777,9 @@ int pic_set_field(pic_ctx* x, int mode, int comp, const void* host_src) {
   if (comp < 6) {
     x->eb_stale = true;
     x->spec_pending = false;
+    launch_pack_gather(x->real, x->gfield, x->nr, x->nz, x->M, x->stream);
+    rc = sync(x);
+    if (rc) return rc;
   } else {
     x->src_set[mode] |= 1u << (comp - kCompJ);
   }

@@ -66,26 +66,30 @@ struct ShapePos {
   float2 eith;
 };
 
+// 1/sqrt(a) for a > 0 to FP64 accuracy: float32 estimate + two Newton steps
+__device__ __forceinline__ double rsqrt_f64(double a) {
+  double y = (double)rsqrtf((float)a);
+  y = y * (1.5 - 0.5 * a * y * y);
+  y = y * (1.5 - 0.5 * a * y * y);
+  return y;
+}
+
 __device__ __forceinline__ ShapePos shape_at(double x, double y, double z, double zmin, const Grid& g) {
   ShapePos s;
   double sz = (z - zmin) * g.inv_dz;
+  sz = fmin(fmax(sz, -1e9), 1e9);
   double fj = floor(sz);
   s.fz = (float)(sz - fj);
-  long long jj = (long long)fj;
-  jj %= g.nz;
-  if (jj < 0) jj += g.nz;
-  s.j0 = (int)jj;
-  double r = sqrt(x * x + y * y);
+  s.j0 = (int)((long long)fj & (long long)(g.nz - 1));   // nz is a power of two: periodic wrap
+  double r2 = x * x + y * y;
+  double ir = r2 > 1e-30 ? rsqrt_f64(r2) : 0.0;
+  double r = r2 * ir;
   double sr = r * g.inv_dr - 0.5;
+  sr = fmin(sr, (double)(1 << 30));
   double fi = floor(sr);
   s.fr = (float)(sr - fi);
-  s.i0 = fi > (double)(1 << 30) ? (1 << 30) : (int)fi;
-  if (r > 0.0) {
-    double ir = 1.0 / r;
-    s.eith = make_float2((float)(x * ir), (float)(y * ir));
-  } else {
-    s.eith = make_float2(1.f, 0.f);
-  }
+  s.i0 = (int)fi;
+  s.eith = r2 > 1e-30 ? make_float2((float)(x * ir), (float)(y * ir)) : make_float2(1.f, 0.f);
   return s;
 }
 

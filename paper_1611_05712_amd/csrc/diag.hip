@@ -160,13 +160,16 @@ __global__ __launch_bounds__(256) void k_collect(Parts p, const DevState* st, Di
   out.w[d] = (float)((double)p.w[i] * sel.inv_q);
 }
 
-__global__ void k_count_alive(Parts p, const DevState* st, DiagSel sel, int* counter) {
+__global__ __launch_bounds__(256) void k_count_alive(Parts p, const DevState* st, DiagSel sel, int* counter) {
+  __shared__ int wsum[4];
   const int n = st->n_part;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool a = false;
-  if (i < n) a = !(sel.kill && p.z[i] < sel.zmin);
-  uint64_t b = __ballot(a);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(counter, __popcll(b));
+  int c = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    c += !(sel.kill && p.z[i] < sel.zmin);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(counter, wsum[0] + wsum[1] + wsum[2] + wsum[3]);
 }
 
 void launch_diag_pass1(const Parts& p, const DevState* st, const DiagSel& sel, double* partial, double* out,
@@ -191,7 +194,9 @@ void launch_collect(const Parts& p, const DevState* st, const DiagSel& sel, int6
 }
 void launch_count_alive(const Parts& p, const DevState* st, const DiagSel& sel, int* counter, int nmax,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_count_alive, dim3((nmax + 255) / 256), dim3(256), 0, s, p, st, sel, counter);
+  int nb = (nmax + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(k_count_alive, dim3(nb), dim3(256), 0, s, p, st, sel, counter);
 }
 
 }  // namespace pic

@@ -37,8 +37,9 @@ void launch_to_f32_transposed(const double* in, float* out, int n, hipStream_t s
 void launch_twiddles(float2* tw, int n, hipStream_t st);
 
 // particles
-void launch_gather_push(const Parts& p, const float2* real, const Grid& g, const SpeciesConst& sc,
+void launch_gather_push(const Parts& p, const float2* gf, const Grid& g, const SpeciesConst& sc,
                         const DevState* st, uint32_t* key, int* count, int cap, hipStream_t s);
+void launch_pack_gather(const float2* real, float2* gf, int nr, int nz, int M, hipStream_t s);
 void launch_keys(const Parts& p, const Grid& g, const DevState* st, uint32_t* key, int* count, int cap,
                  hipStream_t s);
 int scan_scratch_ints(int n);
@@ -47,11 +48,11 @@ void launch_scatter(const Parts& src, const Parts& dst, const uint32_t* key, int
                     int ncells, int cap, hipStream_t s);
 struct DepositShape {
   int TZ, TR, ntz, ntr, ntiles;
+  int halo;             // cells a particle can move per step (1 or 2)
   int max_items;        // workgroups launched (upper bound of the work list)
-  size_t acc_floats2;   // complex accumulators per tile
-  int hz, hr;
+  size_t acc_floats2;   // complex accumulators per block (tile + halo nodes)
 };
-DepositShape deposit_shape(int nz, int nr, int nmodes, int hz, int hr, int64_t cap);
+DepositShape deposit_shape(int nz, int nr, int nmodes, int halo, int64_t cap);
 void launch_deposit(const Parts& p, const int* offset, const DepositShape& d, int* nchunk, int* chunk_start,
                     float2* partial, float2* real, const float2* bg, const Grid& g, DevState* st, hipStream_t s);
 void launch_inject(const Parts& p, DevState* st, const Grid& g, const InjectTable& tab, int cap, hipStream_t s);

@@ -39,80 +39,77 @@ __device__ __forceinline__ RunInfo wave_runs(uint32_t k) {
   return ri;
 }
 
-// --------------------------------------------------------------------------
-// field gather (Cartesian E, B at one position)
-// --------------------------------------------------------------------------
-struct Weights {
-  int ja, jb;        // z nodes
-  int ia, ib;        // radial nodes (ia clamped to 0 for the ghost)
-  float wza, wzb;
-  float wra_even, wra_odd, wrb;   // radial weights incl. fold sign / out-of-box zeroing
-};
-
-__device__ __forceinline__ Weights make_weights(const ShapePos& s, const Grid& g) {
-  Weights w;
-  w.ja = s.j0;
-  w.jb = (s.j0 + 1 == g.nz) ? 0 : s.j0 + 1;
-  w.wza = 1.f - s.fz;
-  w.wzb = s.fz;
-  float wa = 1.f - s.fr, wb = s.fr;
-  int ia = s.i0, ib = s.i0 + 1;
-  if (ia == -1) {
-    w.ia = 0;
-    w.wra_even = wa;
-    w.wra_odd = -wa;
-  } else if (ia >= g.nr || ia < -1) {
-    w.ia = 0;
-    w.wra_even = w.wra_odd = 0.f;
-  } else {
-    w.ia = ia;
-    w.wra_even = w.wra_odd = wa;
+// histogram increment with one atomic per distinct key of the wavefront
+__device__ __forceinline__ void wave_count(uint32_t k, int* __restrict__ count) {
+  const int lane = threadIdx.x & 63;
+  bool todo = k != kInvalidKey;
+  uint64_t pending = __ballot(todo);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t kl = __shfl(k, leader, 64);
+    const bool mine = todo && k == kl;
+    const uint64_t mask = __ballot(mine);
+    if (lane == leader) atomicAdd(&count[kl], __popcll(mask));
+    todo = todo && !mine;
+    pending &= ~mask;
   }
-  if (ib >= g.nr || ib < 0) {
-    w.ib = 0;
-    w.wrb = 0.f;
-  } else {
-    w.ib = ib;
-    w.wrb = wb;
-  }
-  return w;
 }
 
-__device__ __forceinline__ float2 interp(const float2* __restrict__ f, const Weights& w, bool odd, int nz) {
-  float wra = odd ? w.wra_odd : w.wra_even;
-  const float2* ra = f + (size_t)w.ia * nz;
-  const float2* rb = f + (size_t)w.ib * nz;
-  float2 a0 = ra[w.ja], a1 = ra[w.jb], b0 = rb[w.ja], b1 = rb[w.jb];
-  float2 r;
-  r.x = wra * (w.wza * a0.x + w.wzb * a1.x) + w.wrb * (w.wza * b0.x + w.wzb * b1.x);
-  r.y = wra * (w.wza * a0.y + w.wzb * a1.y) + w.wrb * (w.wza * b0.y + w.wzb * b1.y);
-  return r;
+// --------------------------------------------------------------------------
+// field gather.  The gather reads a node-interleaved copy of the real-space
+// E, B: record (i, j) holds, for m = 0..M-1, E+, E-, Ez, B+, B-, Bz of mode m
+// (6M complex float32, 16-byte aligned), so a particle's four nodes are two
+// contiguous segments [(ia, j0), (ia, j0+1)] and [(ib, j0), (ib, j0+1)].
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pack_gather(const float2* __restrict__ real, float2* __restrict__ gf, int nr,
+                                                     int nz, int M) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= (int64_t)nr * nz) return;
+  float2* rec = gf + node * 6 * M;
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) rec[m * 6 + c] = real[fidx(c, m, M, nr, nz) + node];
+}
+
+template <int M>
+struct Gathered {
+  float2 f[M][6];   // E+, E-, Ez, B+, B-, Bz per mode
+};
+
+template <int M>
+__device__ __forceinline__ void gather_node(Gathered<M>& acc, const float2* __restrict__ gf, int i, int j, int nz,
+                                            float w_even, float w_odd) {
+  const float4* rec = reinterpret_cast<const float4*>(gf + ((size_t)i * nz + j) * 6 * M);
+#pragma unroll
+  for (int q = 0; q < 3 * M; ++q) {
+    const float4 v = rec[q];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = 2 * q + h;
+      const int m = e / 6, c = e % 6;
+      // Hankel order: m+1 (E+, B+), m-1 (E-, B-), m (Ez, Bz)
+      const bool odd = (c % 3 == 2) ? (m & 1) : ((m + 1) & 1);
+      const float w = odd ? w_odd : w_even;
+      const float re = h ? v.z : v.x, im = h ? v.w : v.y;
+      acc.f[m][c].x += w * re;
+      acc.f[m][c].y += w * im;
+    }
+  }
 }
 
 // F_z = sum_{m=-M..M} F_{z,m} e^{-i m theta};
 // F_x + i F_y = 2 [ sum_{m>=0} F_{-,m} e^{-i(m-1) theta} + sum_{m>=1} conj(F_{+,m}) e^{i(m+1) theta} ]
-__device__ __forceinline__ void gather_cart(const float2* __restrict__ real, int cbase, const ShapePos& s,
-                                            const Weights& w, const Grid& g, float& fx, float& fy, float& fz) {
-  const int M = g.nmodes, nr = g.nr, nz = g.nz;
-  float2 xy = make_float2(0.f, 0.f);
-  float zz = 0.f;
-  float2 e = s.eith;                       // e^{i theta}
-  float2 em = make_float2(1.f, 0.f);       // e^{i m theta}
-  for (int m = 0; m < M; ++m) {
-    bool odd_m = m & 1;
-    float2 fzm = interp(real + fidx(cbase + 2, m, M, nr, nz), w, odd_m, nz);
-    float2 fmm = interp(real + fidx(cbase + 1, m, M, nr, nz), w, !odd_m, nz);
-    if (m == 0) {
-      zz += fzm.x;
-      xy = cadd(xy, cscale(cmul(fmm, e), 2.f));
-    } else {
-      float2 fpm = interp(real + fidx(cbase + 0, m, M, nr, nz), w, !odd_m, nz);
-      zz += 2.f * cmul(fzm, cconj(em)).x;
-      // e^{-i(m-1) theta} = conj(e^{i m theta}) e^{i theta}
-      float2 t1 = cmul(fmm, cmul(cconj(em), e));
-      float2 t2 = cmul(cconj(fpm), cmul(em, e));
-      xy = cadd(xy, cscale(cadd(t1, t2), 2.f));
-    }
+template <int M>
+__device__ __forceinline__ void cartesian(const Gathered<M>& a, int cb, float2 e, float& fx, float& fy, float& fz) {
+  float2 xy = cscale(cmul(a.f[0][cb + 1], e), 2.f);
+  float zz = a.f[0][cb + 2].x;
+  float2 em = e;
+#pragma unroll
+  for (int m = 1; m < M; ++m) {
+    zz += 2.f * cmul(a.f[m][cb + 2], cconj(em)).x;
+    float2 t1 = cmul(a.f[m][cb + 1], cmul(cconj(em), e));
+    float2 t2 = cmul(cconj(a.f[m][cb + 0]), cmul(em, e));
+    xy = cadd(xy, cscale(cadd(t1, t2), 2.f));
     em = cmul(em, e);
   }
   fx = xy.x;
@@ -120,12 +117,40 @@ __device__ __forceinline__ void gather_cart(const float2* __restrict__ real, int
   fz = zz;
 }
 
+template <int M>
+__device__ __forceinline__ void gather_eb(const float2* __restrict__ gf, const ShapePos& s, const Grid& g, float& Ex,
+                                          float& Ey, float& Ez, float& Bx, float& By, float& Bz) {
+  Gathered<M> a;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a.f[m][c] = make_float2(0.f, 0.f);
+  const int ja = s.j0, jb = (s.j0 + 1 == g.nz) ? 0 : s.j0 + 1;
+  const float wza = 1.f - s.fz, wzb = s.fz;
+  const float wra = 1.f - s.fr, wrb = s.fr;
+  const int ia = s.i0, ib = s.i0 + 1;
+  if (ia == -1) {              // ghost across the axis: node 0 with (-1)^nu
+    gather_node<M>(a, gf, 0, ja, g.nz, wra * wza, -wra * wza);
+    gather_node<M>(a, gf, 0, jb, g.nz, wra * wzb, -wra * wzb);
+  } else if (ia >= 0 && ia < g.nr) {
+    gather_node<M>(a, gf, ia, ja, g.nz, wra * wza, wra * wza);
+    gather_node<M>(a, gf, ia, jb, g.nz, wra * wzb, wra * wzb);
+  }
+  if (ib >= 0 && ib < g.nr) {
+    gather_node<M>(a, gf, ib, ja, g.nz, wrb * wza, wrb * wza);
+    gather_node<M>(a, gf, ib, jb, g.nz, wrb * wzb, wrb * wzb);
+  }
+  cartesian<M>(a, 0, s.eith, Ex, Ey, Ez);
+  cartesian<M>(a, 3, s.eith, Bx, By, Bz);
+}
+
 // --------------------------------------------------------------------------
 // gather + Boris push + move + new cell key + key histogram
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __restrict__ real, Grid g,
-                                                     SpeciesConst sc, const DevState* __restrict__ st,
-                                                     uint32_t* __restrict__ key, int* __restrict__ count) {
+template <int M>
+__global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __restrict__ gf, Grid g, SpeciesConst sc,
+                                                     const DevState* __restrict__ st, uint32_t* __restrict__ key,
+                                                     int* __restrict__ count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = st->n_part;
   const double zmin = st->zmin;
@@ -140,10 +165,8 @@ __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __re
       float ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
       float qm = sc.qm[p.sp[i]];
       ShapePos s = shape_at(x, y, z, zmin, g);
-      Weights w = make_weights(s, g);
       float Ex, Ey, Ez, Bx, By, Bz;
-      gather_cart(real, 0, s, w, g, Ex, Ey, Ez);
-      gather_cart(real, 3, s, w, g, Bx, By, Bz);
+      gather_eb<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
       // Boris rotation (J. P. Boris, 1970)
       float eps = qm * (float)g.dt * 0.5f;
       float umx = ux + eps * Ex, umy = uy + eps * Ey, umz = uz + eps * Ez;
@@ -174,8 +197,7 @@ __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __re
     }
     key[i] = k;
   }
-  RunInfo ri = wave_runs(k);
-  if (ri.head && k != kInvalidKey) atomicAdd(&count[k], ri.len);
+  wave_count(k, count);
 }
 
 // key + histogram of the current positions (no push): background deposit at setup
@@ -188,8 +210,7 @@ __global__ __launch_bounds__(256) void k_keys(Parts p, Grid g, const DevState* _
     k = cell_key(shape_at(p.x[i], p.y[i], p.z[i], st->zmin, g), g);
     key[i] = k;
   }
-  RunInfo ri = wave_runs(k);
-  if (ri.head && k != kInvalidKey) atomicAdd(&count[k], ri.len);
+  wave_count(k, count);
 }
 
 // --------------------------------------------------------------------------
@@ -271,30 +292,87 @@ __global__ __launch_bounds__(256) void k_scan_apply(int* __restrict__ count, int
 }
 
 // --------------------------------------------------------------------------
-// scatter into cell order (removed particles dropped)
+// scatter into cell order (removed particles dropped).  Block-level
+// multisplit: the 256 keys of a block are sorted in LDS (bitonic, key then
+// original index, so the order is stable), every distinct key reserves one
+// contiguous range of its cell with a single atomic, and thread t writes the
+// t-th particle of the sorted block, so particles bound for one cell leave
+// as one contiguous run even when the wake has scrambled the input order.
 // --------------------------------------------------------------------------
+struct PartRec {
+  double x, y, z;
+  float ux, uy, uz, w;
+  uint32_t sp;
+};
+
 __global__ __launch_bounds__(256) void k_scatter(Parts src, Parts dst, const uint32_t* __restrict__ key,
                                                  int* __restrict__ cursor, const DevState* __restrict__ st,
                                                  int ncells) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint64_t sk[256];     // (key << 32) | local index
+  __shared__ PartRec rec[256];
+  __shared__ int base_of[256];     // destination of sorted slot t
+  const int tid = threadIdx.x;
+  const int i = blockIdx.x * 256 + tid;
   const int n = st->n_part;
   uint32_t k = (i < n) ? key[i] : kInvalidKey;
-  if (k == (uint32_t)ncells) k = kInvalidKey;   // removed
-  RunInfo ri = wave_runs(k);
-  int base = 0;
-  if (ri.head && k != kInvalidKey) base = atomicAdd(&cursor[k], ri.len);
-  const int lane = threadIdx.x & 63;
-  base = __shfl(base, ri.head_lane, 64);
+  if (k >= (uint32_t)ncells) k = kInvalidKey;   // removed or past the end
+  sk[tid] = ((uint64_t)k << 32) | (uint32_t)tid;
   if (k != kInvalidKey) {
-    int d = base + (lane - ri.head_lane);
-    dst.x[d] = src.x[i];
-    dst.y[d] = src.y[i];
-    dst.z[d] = src.z[i];
-    dst.ux[d] = src.ux[i];
-    dst.uy[d] = src.uy[i];
-    dst.uz[d] = src.uz[i];
-    dst.w[d] = src.w[i];
-    dst.sp[d] = src.sp[i];
+    PartRec r;
+    r.x = src.x[i];
+    r.y = src.y[i];
+    r.z = src.z[i];
+    r.ux = src.ux[i];
+    r.uy = src.uy[i];
+    r.uz = src.uz[i];
+    r.w = src.w[i];
+    r.sp = src.sp[i];
+    rec[tid] = r;
+  }
+  __syncthreads();
+  // bitonic sort of 256 64-bit keys
+  for (int size = 2; size <= 256; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const int partner = tid ^ stride;
+      if (partner > tid) {
+        const bool up = (tid & size) == 0;
+        const uint64_t a = sk[tid], b = sk[partner];
+        if ((a > b) == up) {
+          sk[tid] = b;
+          sk[partner] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const uint64_t me = sk[tid];
+  const uint32_t mk = (uint32_t)(me >> 32);
+  const bool first = (tid == 0) || ((uint32_t)(sk[tid - 1] >> 32) != mk);
+  const bool last = (tid == 255) || ((uint32_t)(sk[tid + 1] >> 32) != mk);
+  // head of each run: inclusive prefix maximum of (first ? index : 0)
+  base_of[tid] = first ? tid : 0;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = tid >= off ? base_of[tid - off] : 0;
+    __syncthreads();
+    if (v > base_of[tid]) base_of[tid] = v;
+    __syncthreads();
+  }
+  const int h = base_of[tid];
+  __syncthreads();
+  if (last && mk != kInvalidKey) base_of[h] = atomicAdd(&cursor[mk], tid - h + 1);
+  __syncthreads();
+  if (mk != kInvalidKey) {
+    const int d = base_of[h] + (tid - h);
+    const PartRec& r = rec[(uint32_t)me];
+    dst.x[d] = r.x;
+    dst.y[d] = r.y;
+    dst.z[d] = r.z;
+    dst.ux[d] = r.ux;
+    dst.uy[d] = r.uy;
+    dst.uz[d] = r.uz;
+    dst.w[d] = r.w;
+    dst.sp[d] = (uint8_t)r.sp;
   }
 }
 
@@ -357,9 +435,18 @@ __global__ void k_uniform_check(const float2* __restrict__ rho, int rows, int nz
 // --------------------------------------------------------------------------
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
-void launch_gather_push(const Parts& p, const float2* real, const Grid& g, const SpeciesConst& sc,
+void launch_gather_push(const Parts& p, const float2* gf, const Grid& g, const SpeciesConst& sc,
                         const DevState* st, uint32_t* key, int* count, int cap, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_push, dim3(nblk(cap, 256)), dim3(256), 0, s, p, real, g, sc, st, key, count);
+  dim3 grid(nblk(cap, 256));
+  switch (g.nmodes) {
+    case 1: hipLaunchKernelGGL(k_gather_push<1>, grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+    case 2: hipLaunchKernelGGL(k_gather_push<2>, grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+    case 3: hipLaunchKernelGGL(k_gather_push<3>, grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+    default: hipLaunchKernelGGL(k_gather_push<4>, grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+  }
+}
+void launch_pack_gather(const float2* real, float2* gf, int nr, int nz, int M, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_gather, dim3(nblk((int64_t)nr * nz, 256)), dim3(256), 0, s, real, gf, nr, nz, M);
 }
 void launch_keys(const Parts& p, const Grid& g, const DevState* st, uint32_t* key, int* count, int cap,
                  hipStream_t s) {
