@@ -34,7 +34,7 @@ MFMA_BF16_TFLOPS = 2500.0      # dense bf16 / fp16
 # algorithmic traffic per unit of work (bytes), see the design doc
 BYTES_PER_PARTICLE = {
     "gather_push": 78.0,   # read x,y,z (24) + u (12); write 36; field share ~6
-    "sort": 86.0,          # read key (4) + particle (41); write particle (41)
+    "sort": 86.0,          # scatter: read key (4) + particle (41); write particle (41)
     "deposit": 45.0,       # read x,y,z (24) + u (12) + w (4); grid share ~5
 }
 BYTES_PER_CELL = {
@@ -65,6 +65,12 @@ def _phase_units(name, wl, n_part, prec):
         return BYTES_PER_CELL[name] * 6 * cells / 1e9, "GB/s", "hbm", HBM_PEAK_GBS
     if name == "psatd":
         return BYTES_PER_CELL[name] * nr * nz * M / 1e9, "GB/s", "hbm", HBM_PEAK_GBS
+    if name == "scan":          # count read, offset + cursor written, count cleared, per cell key
+        return 16.0 * nz * (nr + 1) / 1e9, "GB/s", "hbm", HBM_PEAK_GBS
+    if name == "dep_combine":   # 5 source components written, ion background read (2)
+        return 8.0 * 7 * cells / 1e9, "GB/s", "hbm", HBM_PEAK_GBS
+    if name == "pack":          # 6 field components read and written once
+        return 8.0 * 12 * cells / 1e9, "GB/s", "hbm", HBM_PEAK_GBS
     if name in ("dht_fwd", "dht_inv"):
         batch = (5 if name == "dht_fwd" else 6) * M
         flops = 2.0 * nr * nr * (2 * nz) * batch
@@ -175,7 +181,7 @@ def main():
 
     cells = wl.nz * wl.nr * wl.n_modes
     spectral_ms = sum(times[k][0] for k in ("fft_fwd", "dht_fwd", "psatd", "dht_inv", "fft_inv",
-                                             "window"))
+                                             "pack", "window"))
     kernels = {}
     for name, (tot_ms, nl) in times.items():
         if nl == 0:

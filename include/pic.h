@@ -110,7 +110,8 @@ typedef struct {
   double density;     /* injected lattice density (units of n0) */
   int32_t diag;       /* 1: species selectable by pic_diagnostics */
   const double *x, *y, *z;            /* host, length n */
-  const float *ux, *uy, *uz, *w;      /* host, length n; w = macro-particle weight */
+  const float *ux, *uy, *uz, *w;      /* host, length n; u = gamma beta (u_z is widened
+                                         to FP64 on the device); w = macro-particle weight */
 } pic_species;
 
 /* Bytes of device workspace needed for cfg, the species and a particle capacity
@@ -195,10 +196,13 @@ int pic_set_field(pic_ctx* ctx, int mode, int comp, const void* host_src);
 int pic_num_particles(pic_ctx* ctx, int64_t* n);
 
 /* Copies the live mobile particles of one species (index into the pic_init
- * array) to host: xyz = n*3 doubles (x, y, z per particle), uvw = n*3 floats,
+ * array) to host: xyz = n*3 doubles (x, y, z per particle), uvw = n*3 doubles
+ * (u_x, u_y, u_z: the library keeps u_x, u_y in FP32 and u_z in FP64),
  * w = n floats (may be NULL); at most `cap` particles, count in *n.
- * Order is the library's current storage order.  Synchronizes. */
-int pic_get_particles(pic_ctx* ctx, int species, int64_t cap, double* xyz, float* uvw,
+ * Order is the library's current storage order.  Synchronizes.
+ * Errors: PIC_EINVAL (null pointer, bad species), PIC_ENOSPC (more than cap
+ * particles: the first cap are copied), PIC_EHIP. */
+int pic_get_particles(pic_ctx* ctx, int species, int64_t cap, double* xyz, double* uvw,
                       float* w, int64_t* n);
 
 /* Current window position z_min and number of completed steps. */
@@ -218,15 +222,19 @@ const char* pic_strerror(int status);
  * ------------------------------------------------------------------------ */
 typedef enum {
   PIC_T_GATHER_PUSH = 0, /* gather + Boris push kernel */
-  PIC_T_SORT = 1,        /* bucket scan + scatter */
-  PIC_T_DEPOSIT = 2,     /* tile deposit kernel */
+  PIC_T_SORT = 1,        /* particle scatter into cell order */
+  PIC_T_DEPOSIT = 2,     /* tile deposit kernel (LDS accumulation of one tile or chunk) */
   PIC_T_FFT_FWD = 3,     /* forward z-FFT of the sources (and of E, B when re-transformed) */
   PIC_T_DHT_FWD = 4,     /* forward Hankel-transform products */
   PIC_T_PSATD = 5,       /* window shift + current correction + PSATD update */
   PIC_T_DHT_INV = 6,     /* inverse Hankel-transform products of E, B */
   PIC_T_FFT_INV = 7,     /* inverse z-FFT of E, B (+ window shift) */
   PIC_T_WINDOW = 8,      /* departed-column transform, window advance, injection */
-  PIC_T_N = 9
+  PIC_T_SCAN = 9,        /* exclusive scan of the per-cell particle counts */
+  PIC_T_DEP_PLAN = 10,   /* deposit work list: particles per tile, chunk offsets */
+  PIC_T_DEP_COMBINE = 11,/* node-parallel sum of the tile blocks into the grid */
+  PIC_T_PACK = 12,       /* node-interleaved copy of E, B for the gather */
+  PIC_T_N = 13
 } pic_timer;
 
 /* enable != 0 clears previous records and starts recording; 0 stops. */

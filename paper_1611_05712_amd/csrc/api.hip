@@ -5,7 +5,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "../../include/pic.h"
+#include "pic.h"
 #include "common.h"
 #include "launch.h"
 
@@ -205,9 +205,9 @@ size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
     pp[b].x = cv.take<double>(cap);
     pp[b].y = cv.take<double>(cap);
     pp[b].z = cv.take<double>(cap);
+    pp[b].uz = cv.take<double>(cap);
     pp[b].ux = cv.take<float>(cap);
     pp[b].uy = cv.take<float>(cap);
-    pp[b].uz = cv.take<float>(cap);
     pp[b].w = cv.take<float>(cap);
     pp[b].sp = cv.take<uint8_t>(cap);
   }
@@ -392,6 +392,17 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
   if (bytes < need) return PIC_ENOSPC;
   Counts cnt = count_species(cfg, species, n_species);
   if (cnt.mobile > cap) return PIC_ENOSPC;
+  {
+    // the deposit's FP64 tile block must fit one workgroup's LDS
+    const DepositShape dep = deposit_shape(cfg->nz, cfg->nr, cfg->n_modes,
+                                           std::max(halo_cells(cfg->dt, cfg->dz), halo_cells(cfg->dt, cfg->dr)),
+                                           cap);
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      return PIC_EHIP;
+    if (dep.lds_bytes + 1024 > (size_t)lds_max) return PIC_EINVAL;
+  }
 
   pic_ctx* x = new pic_ctx();   // value-initialized: every scalar member starts at zero
   x->cfg = *cfg;
@@ -531,14 +542,14 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
     }
     launch_fill_zero(P.ux, cap * sizeof(float), s);
     launch_fill_zero(P.uy, cap * sizeof(float), s);
-    launch_fill_zero(P.uz, cap * sizeof(float), s);
+    launch_fill_zero(P.uz, cap * sizeof(double), s);
     launch_fill_zero(P.sp, cap, s);
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, x->st, cfg->z_min, (int)off);
     launch_keys(P, g, x->st, x->key, x->count, (int)cap, s);
     launch_scan(x->count, g.ncells + 1, x->bsum, x->offset, x->cursor, g.ncells, x->st, s);
     launch_scatter(P, x->parts[0], x->key, x->cursor, x->st, g.ncells, (int)cap, s);
     launch_deposit(x->parts[0], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real, nullptr, g,
-                   x->st, s);
+                   x->st, kDepAll, s);
     if (cfg->moving_window) {
       launch_uniform_check(fld(x->real, x, kCompJ + 4, 0), M * nr, nz, (unsigned*)(x->misc + 1), s);
     }
@@ -556,6 +567,7 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
       const pic_species& p = species[i];
       if (!p.mobile || p.n == 0) continue;
       std::vector<float> qw(p.n);
+      std::vector<double> uz(p.uz, p.uz + p.n);
       std::vector<uint8_t> id(p.n, (uint8_t)i);
       for (int64_t k = 0; k < p.n; ++k) qw[k] = (float)(p.q * (double)p.w[k]);
       PIC_CK(hipMemcpyAsync(P.x + off, p.x, p.n * sizeof(double), hipMemcpyHostToDevice, s));
@@ -563,7 +575,7 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
       PIC_CK(hipMemcpyAsync(P.z + off, p.z, p.n * sizeof(double), hipMemcpyHostToDevice, s));
       PIC_CK(hipMemcpyAsync(P.ux + off, p.ux, p.n * sizeof(float), hipMemcpyHostToDevice, s));
       PIC_CK(hipMemcpyAsync(P.uy + off, p.uy, p.n * sizeof(float), hipMemcpyHostToDevice, s));
-      PIC_CK(hipMemcpyAsync(P.uz + off, p.uz, p.n * sizeof(float), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.uz + off, uz.data(), p.n * sizeof(double), hipMemcpyHostToDevice, s));
       PIC_CK(hipMemcpyAsync(P.w + off, qw.data(), p.n * sizeof(float), hipMemcpyHostToDevice, s));
       PIC_CK(hipMemcpyAsync(P.sp + off, id.data(), p.n, hipMemcpyHostToDevice, s));
       PIC_CK(hipStreamSynchronize(s));
@@ -612,16 +624,22 @@ int pic_deposit(pic_ctx* x) {
   if (x->phase != 1) return PIC_ESTATE;
   const Grid& g = x->g;
   {
-    Phase ph(x, PIC_T_SORT);
+    Phase ph(x, PIC_T_SCAN);
     launch_scan(x->count, g.ncells + 1, x->bsum, x->offset, x->cursor, g.ncells, x->st, x->stream);
+  }
+  {
+    Phase ph(x, PIC_T_SORT);
     launch_scatter(x->parts[x->cur], x->parts[x->cur ^ 1], x->key, x->cursor, x->st, g.ncells, (int)x->cap,
                    x->stream);
   }
   x->cur ^= 1;
-  {
-    Phase ph(x, PIC_T_DEPOSIT);
-    launch_deposit(x->parts[x->cur], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real,
-                   x->have_bg ? x->bg : nullptr, g, x->st, x->stream);
+  const float2* bg = x->have_bg ? x->bg : nullptr;
+  const int stage[3] = {kDepPlan, kDepTiles, kDepCombine};
+  const int timer[3] = {PIC_T_DEP_PLAN, PIC_T_DEPOSIT, PIC_T_DEP_COMBINE};
+  for (int k = 0; k < 3; ++k) {
+    Phase ph(x, timer[k]);
+    launch_deposit(x->parts[x->cur], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real, bg,
+                   g, x->st, stage[k], x->stream);
   }
   x->phase = 2;
   return check_launch();
@@ -658,6 +676,9 @@ int pic_spectral_push(pic_ctx* x) {
   {
     Phase ph(x, PIC_T_FFT_INV);
     launch_fft(fld(x->tmp, x, 0, 0), fld(x->real, x, 0, 0), x->tw, nz, (int64_t)6 * M * nr, true, mw, x->tail, s);
+  }
+  {
+    Phase ph(x, PIC_T_PACK);
     launch_pack_gather(x->real, x->gfield, nr, nz, M, s);
   }
   if (mw) {
@@ -708,7 +729,7 @@ int pic_num_particles(pic_ctx* x, int64_t* n) {
   return PIC_OK;
 }
 
-int pic_get_particles(pic_ctx* x, int species, int64_t cap, double* xyz, float* uvw, float* w, int64_t* n) {
+int pic_get_particles(pic_ctx* x, int species, int64_t cap, double* xyz, double* uvw, float* w, int64_t* n) {
   if (!x || !xyz || !uvw || !n || species < 0 || species >= x->n_species || cap < 0) return PIC_EINVAL;
   if (!x->sp[species].mobile) return PIC_EINVAL;
   int rc = sync(x);
@@ -729,14 +750,14 @@ int pic_get_particles(pic_ctx* x, int species, int64_t cap, double* xyz, float* 
   int cnt;
   if (hipMemcpy(&cnt, counter, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
   int64_t got = std::min<int64_t>(cnt, lim);
-  std::vector<double> hx(got), hy(got), hz(got);
-  std::vector<float> hu(got), hv(got), hw(got), hq(got);
+  std::vector<double> hx(got), hy(got), hz(got), hw(got);
+  std::vector<float> hu(got), hv(got), hq(got);
   bool ok = hipMemcpy(hx.data(), stage.x, got * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
             hipMemcpy(hy.data(), stage.y, got * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
             hipMemcpy(hz.data(), stage.z, got * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
             hipMemcpy(hu.data(), stage.ux, got * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess &&
             hipMemcpy(hv.data(), stage.uy, got * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess &&
-            hipMemcpy(hw.data(), stage.uz, got * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(hw.data(), stage.uz, got * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
             hipMemcpy(hq.data(), stage.w, got * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess;
   if (!ok) return PIC_EHIP;
   for (int64_t k = 0; k < got; ++k) {

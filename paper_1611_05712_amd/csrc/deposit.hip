@@ -13,12 +13,14 @@
 //     device builds this work list (k_tile_plan) from the sorted offsets;
 //   * k_deposit_combine sums, node by node, the slots of every block covering
 //     the node and writes the grid.
-// Within a wavefront consecutive lanes hold consecutive (cell-sorted)
-// particles.  For each of the three positions, lanes sharing a cell form
-// runs; the node contributions are summed along each run with DPP row shifts
-// (runs are cut at 16-lane row boundaries) and only the run head issues the
-// LDS atomics.  Waves whose particles are all at rest deposit rho once (it is
-// rho^n and rho^{n+1}) and no current.
+// Within a workgroup every lane takes short runs of consecutive cell-sorted
+// particles.  Particles of one cell share their four nodes, so a lane sums
+// the node contributions of each of the three positions in registers and
+// issues the LDS atomics only when that position's cell changes (and once at
+// the end).  Beam cores with thousands of particles per cell then cost one
+// flush per lane rather than one atomic per particle, and neighbouring lanes'
+// flushes rarely hit the same node.  Waves whose particles are all at rest skip the current and
+// reuse the x^{n+1} shape for rho^n.
 #include "common.h"
 #include "launch.h"
 
@@ -26,6 +28,7 @@ namespace pic {
 
 constexpr int kChunk = 16384;   // max particles per workgroup
 constexpr int kTZ = 32;
+constexpr int kRun = 8;       // consecutive particles per lane per sub-chunk
 
 __device__ __forceinline__ size_t dfidx(int c, int m, int M, int nr, int nz) {
   return ((size_t)c * M + m) * (size_t)nr * nz;
@@ -89,80 +92,20 @@ __global__ __launch_bounds__(1024) void k_tile_plan(const int* __restrict__ nchu
 }
 
 // ---------------------------------------------------------------------------
-// run reduction along DPP rows
-// ---------------------------------------------------------------------------
-template <int CTRL>
-__device__ __forceinline__ float row_shl(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-
-struct RunMask {
-  int dist;              // lanes after this one in its run (within the row)
-  bool head;
-  bool s1, s2, s4, s8;   // wave-uniform: some run needs this step
+// Compact value layout of a block (FP64 in LDS, FP32 in the scratch slot),
+// [value][node]: mode 0 holds J+ (re, im), Jz, rho^n, rho^{n+1} (the mode-0
+// densities and J_z are real, J-,0 = conj(J+,0) is rebuilt by the combine);
+// each mode m >= 1 holds J+, J-, Jz, rho^n, rho^{n+1}, complex.
+template <int M>
+struct Vals {
+  static constexpr int N = 5 + 10 * (M - 1);
 };
-
-__device__ __forceinline__ RunMask run_mask(uint32_t key) {
-  const int lane = threadIdx.x & 63;
-  const uint32_t prev = __shfl_up(key, 1, 64);
-  const bool head = ((lane & 15) == 0) || (prev != key);
-  const uint64_t heads = __ballot(head);
-  const uint64_t after = (lane == 63) ? 0ull : (heads & ~((2ull << lane) - 1ull));
-  const int next = after ? (__ffsll((long long)after) - 1) : 64;
-  RunMask rm;
-  rm.head = head;
-  rm.dist = next - lane - 1;
-  rm.s1 = __ballot(rm.dist >= 1) != 0;
-  rm.s2 = __ballot(rm.dist >= 2) != 0;
-  rm.s4 = __ballot(rm.dist >= 4) != 0;
-  rm.s8 = __ballot(rm.dist >= 8) != 0;
-  return rm;
-}
-
-// r[i] <- sum of r[i] over lanes l .. l + dist (one wave-uniform branch per
-// step; the n independent shifts of a step interleave)
-template <int N>
-__device__ __forceinline__ void run_reduce(float (&r)[N], const RunMask& rm) {
-  if (rm.s1) {
-    const bool c = rm.dist >= 1;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const float t = row_shl<0x101>(r[i]);
-      r[i] += c ? t : 0.f;
-    }
-  }
-  if (rm.s2) {
-    const bool c = rm.dist >= 2;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const float t = row_shl<0x102>(r[i]);
-      r[i] += c ? t : 0.f;
-    }
-  }
-  if (rm.s4) {
-    const bool c = rm.dist >= 4;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const float t = row_shl<0x104>(r[i]);
-      r[i] += c ? t : 0.f;
-    }
-  }
-  if (rm.s8) {
-    const bool c = rm.dist >= 8;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const float t = row_shl<0x108>(r[i]);
-      r[i] += c ? t : 0.f;
-    }
-  }
-}
+__device__ __forceinline__ constexpr int vbase(int m) { return m == 0 ? 0 : 5 + 10 * (m - 1); }
 
 // ---------------------------------------------------------------------------
-// per-position values and their place in the LDS block.  Block layout:
-// [slot][m][br][bz] complex (slot 0 J+, 1 J-, 2 Jz, 3 rho^n, 4 rho^{n+1});
-// the mode-0 density and J_z are real, J-,0 = conj(J+,0) is rebuilt by the
-// combine.  Each value k has a compile-time float offset and the parity of
-// its Hankel order (sign of the ghost node across the axis).
+// per-position values and their place in the block: each value k has a
+// compile-time offset (value index times the block's node count) and the
+// parity of its Hankel order (sign of the ghost node across the axis).
 // ---------------------------------------------------------------------------
 template <int M, int NODES>
 struct RhoSet {
@@ -170,8 +113,9 @@ struct RhoSet {
   static __device__ __forceinline__ constexpr int mode(int k) { return k == 0 ? 0 : 1 + (k - 1) / 2; }
   static __device__ __forceinline__ constexpr int part(int k) { return k == 0 ? 0 : (k - 1) & 1; }
   static __device__ __forceinline__ constexpr int parity(int k) { return mode(k) & 1; }
+  // slot 3: rho^n, slot 4: rho^{n+1}
   static __device__ __forceinline__ constexpr int off(int slot, int k) {
-    return 2 * (slot * M + mode(k)) * NODES + part(k);
+    return (k == 0 ? slot : vbase(mode(k)) + (slot == 3 ? 6 : 8) + part(k)) * NODES;
   }
   static __device__ __forceinline__ void values(float qw, float2 e, float (&v)[K]) {
     v[0] = qw;
@@ -196,7 +140,7 @@ struct JSet {
     return slot(k) == 2 ? (mode(k) & 1) : ((mode(k) + 1) & 1);
   }
   static __device__ __forceinline__ constexpr int off(int k) {
-    return 2 * (slot(k) * M + mode(k)) * NODES + part(k);
+    return (k < 3 ? k : vbase(mode(k)) + (k - 3) % 6) * NODES;
   }
   static __device__ __forceinline__ void values(float qw, float vx, float vy, float vz, float2 e, float (&v)[K]) {
     // J+ = qw (vx - i vy)/2 e^{i(m+1)theta}; J- = qw (vx + i vy)/2 e^{i(m-1)theta}; Jz = qw vz e^{i m theta}
@@ -254,51 +198,87 @@ __device__ __forceinline__ Local<TR, H> localize(const ShapePos& s, const Grid& 
   return L;
 }
 
-// products with the four node weights, run reduction, head flush
-template <int K, class Set, class OffFn>
-__device__ __forceinline__ void deposit_set(float* __restrict__ lds, const float (&v)[K], bool valid, const RunMask& rm,
-                                            const ShapePos& s, int na, int nb, float sa_even, float sa_odd,
-                                            float sb, OffFn off) {
-  const float fz = s.fz, fr = s.fr;
-  const float w0 = (1.f - fz) * (1.f - fr), w1 = fz * (1.f - fr), w2 = (1.f - fz) * fr, w3 = fz * fr;
-  float r[4 * K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const float vk = valid ? v[k] : 0.f;
-    r[4 * k + 0] = w0 * vk;   // (ia, j0)
-    r[4 * k + 1] = w1 * vk;   // (ia, j0 + 1)
-    r[4 * k + 2] = w2 * vk;   // (ib, j0)
-    r[4 * k + 3] = w3 * vk;   // (ib, j0 + 1)
-  }
-  run_reduce<4 * K>(r, rm);
-  if (rm.head && valid) {
-    float* pa = lds + 2 * na;
-    float* pb = lds + 2 * nb;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const float sa = Set::parity(k) ? sa_odd : sa_even;
-      const int o = off(k);
-      atomicAdd(pa + o, sa * r[4 * k + 0]);
-      atomicAdd(pa + o + 2, sa * r[4 * k + 1]);
-      atomicAdd(pb + o, sb * r[4 * k + 2]);
-      atomicAdd(pb + o + 2, sb * r[4 * k + 3]);
-    }
-  }
-}
-
 __device__ __forceinline__ uint32_t pos_key(const ShapePos& s, int nr) {
   const int ic = (s.i0 > nr ? nr : s.i0) + 1;
   return (uint32_t)s.j0 * 2048u + (uint32_t)ic;
 }
 
+// Register accumulator of one position kind: the cell key it belongs to and
+// the K values times the four node weights (ia,j0), (ia,j0+1), (ib,j0), (ib,j0+1).
+template <int K>
+struct Acc {
+  uint32_t key;
+  float a[4 * K];
+};
+
+template <int K>
+__device__ __forceinline__ void acc_reset(Acc<K>& A, uint32_t key) {
+  A.key = key;
+#pragma unroll
+  for (int i = 0; i < 4 * K; ++i) A.a[i] = 0.f;
+}
+
+template <int K>
+__device__ __forceinline__ void acc_add(Acc<K>& A, const float (&v)[K], float fz, float fr) {
+  const float w0 = (1.f - fz) * (1.f - fr), w1 = fz * (1.f - fr), w2 = (1.f - fz) * fr, w3 = fz * fr;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    A.a[4 * k + 0] += w0 * v[k];
+    A.a[4 * k + 1] += w1 * v[k];
+    A.a[4 * k + 2] += w2 * v[k];
+    A.a[4 * k + 3] += w3 * v[k];
+  }
+}
+
+// LDS atomics (FP64) of one accumulator at the nodes of its cell key
+template <int TR, int H, int K, class Set, class OffFn>
+__device__ __forceinline__ void acc_flush(double* __restrict__ lds, const Acc<K>& A, const Grid& g, int J0, int C0,
+                                          OffFn off) {
+  ShapePos s;
+  s.j0 = (int)(A.key >> 11);
+  s.i0 = (int)(A.key & 2047u) - 1;
+  const Local<TR, H> L = localize<TR, H>(s, g, J0, C0);
+  if (L.sb != 0.f) {
+    double* pb = lds + L.nb;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int o = off(k);
+      atomicAdd(pb + o, (double)A.a[4 * k + 2]);
+      atomicAdd(pb + o + 1, (double)A.a[4 * k + 3]);
+    }
+  }
+  if (L.sa_even != 0.f) {
+    double* pa = lds + L.na;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float sa = Set::parity(k) ? L.sa_odd : L.sa_even;
+      const int o = off(k);
+      atomicAdd(pa + o, (double)(sa * A.a[4 * k + 0]));
+      atomicAdd(pa + o + 1, (double)(sa * A.a[4 * k + 1]));
+    }
+  }
+}
+
+// one position of one particle: flush the accumulator if the cell changed,
+// then add the node contributions
+template <int TR, int H, int K, class Set, class OffFn>
+__device__ __forceinline__ void acc_step(double* __restrict__ lds, Acc<K>& A, uint32_t key, const float (&v)[K],
+                                         const ShapePos& s, const Grid& g, int J0, int C0, OffFn off) {
+  if (key != A.key) {
+    if (A.key != kInvalidKey) acc_flush<TR, H, K, Set>(lds, A, g, J0, C0, off);
+    acc_reset(A, key);
+  }
+  acc_add(A, v, s.fz, s.fr);
+}
+
 template <int TR, int H, int M>
 __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict__ offset,
                                                  const int* __restrict__ nchunk, const int* __restrict__ chunk_start,
-                                                 float2* __restrict__ scratch, Grid g, TileGeom tg, DevState* st) {
+                                                 float* __restrict__ scratch, Grid g, TileGeom tg, DevState* st) {
   using B = Blk<TR, H>;
   using RS = RhoSet<M, B::NODES>;
   using JS = JSet<M, B::NODES>;
-  extern __shared__ float2 lds_blk[];
+  extern __shared__ double lds[];
   __shared__ int rowstart[kTZ];
   __shared__ int rowpref[kTZ + 1];
   __shared__ int s_tile;
@@ -318,8 +298,8 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
     }
     s_tile = lo;
   }
-  constexpr int nacc = 5 * M * B::NODES;
-  for (int e = tid; e < nacc; e += blockDim.x) lds_blk[e] = make_float2(0.f, 0.f);
+  constexpr int nacc = Vals<M>::N * B::NODES;
+  for (int e = tid; e < nacc; e += blockDim.x) lds[e] = 0.0;
   __syncthreads();
   const int t = s_tile;
   const int chunk = b - chunk_start[t];
@@ -340,75 +320,93 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
   const int total = rowpref[kTZ];
   const int f0 = chunk * kChunk;
   const int f1 = min(total, f0 + kChunk);
-  float* lds = (float*)lds_blk;
   const double zmin = st->zmin;
   const double dt = g.dt;
-  const int lane = tid & 63, wave = tid >> 6;
-  for (int base = f0 + wave * 64; base < f1; base += 256) {
-    const int f = base + lane;
-    const bool valid = f < f1;
-    double x = 0.0, y = 0.0, z = zmin;
-    float ux = 0.f, uy = 0.f, uz = 0.f, qw = 0.f;
-    if (valid) {
+  Acc<RS::K> An, A1;
+  Acc<JS::K> AJ;
+  acc_reset(An, kInvalidKey);
+  acc_reset(A1, kInvalidKey);
+  acc_reset(AJ, kInvalidKey);
+  // The chunk is walked in sub-chunks of 256 * kRun particles; in each, lane
+  // tid takes the kRun consecutive particles from tid * kRun.  A sub-chunk's
+  // particle data stays cache resident while its lanes consume it, and a lane
+  // keeps its accumulators across sub-chunks (long runs of one cell in dense
+  // beams flush once).
+  for (int sb = f0; sb < f1; sb += 256 * kRun) {
+    int f = sb + tid * kRun;
+    const int fe = min(f + kRun, f1);
+    int row = 0, row_end = 0, row_base = 0;
+    if (f < fe) {
       int lo = 0, hi = kTZ;   // rowpref[lo] <= f < rowpref[hi]
-#pragma unroll
-      for (int it = 0; it < 5; ++it) {
+      while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (rowpref[mid] <= f) lo = mid;
         else hi = mid;
       }
-      const int idx = rowstart[lo] + (f - rowpref[lo]);
-      x = p.x[idx];
-      y = p.y[idx];
-      z = p.z[idx];
-      ux = p.ux[idx];
-      uy = p.uy[idx];
-      uz = p.uz[idx];
-      qw = p.w[idx];
+      row = lo;
+      row_end = rowpref[lo + 1];
+      row_base = rowstart[lo] - rowpref[lo];
     }
-    const bool cold = __ballot(valid && (ux != 0.f || uy != 0.f || uz != 0.f)) == 0;
-    const float ginv = 1.f / sqrtf(1.f + ux * ux + uy * uy + uz * uz);
-    const float vx = ux * ginv, vy = uy * ginv, vz = uz * ginv;
-    // rho^{n+1} at x^{n+1} (also rho^n when the whole wave is at rest)
-    {
-      const ShapePos s = shape_at(x, y, z, zmin, g);
-      const RunMask rm = run_mask(valid ? pos_key(s, g.nr) : kInvalidKey);
-      const Local<TR, H> L = localize<TR, H>(s, g, J0, C0);
-      float v[RS::K];
-      RS::values(qw, s.eith, v);
-      deposit_set<RS::K, RS>(lds, v, valid, rm, s, L.na, L.nb, L.sa_even, L.sa_odd, L.sb,
-                             [](int k) { return RS::off(4, k); });
-      if (cold) {
-        deposit_set<RS::K, RS>(lds, v, valid, rm, s, L.na, L.nb, L.sa_even, L.sa_odd, L.sb,
-                               [](int k) { return RS::off(3, k); });
-        continue;
+    for (int it = 0; it < kRun; ++it, ++f) {
+      const bool valid = f < fe;
+      double x = 0.0, y = 0.0, z = zmin;
+      float ux = 0.f, uy = 0.f, uz = 0.f, qw = 0.f;
+      if (valid) {
+        while (f >= row_end) {   // skips empty rows; row < kTZ - 1 here since f < total
+          ++row;
+          row_end = rowpref[row + 1];
+          row_base = rowstart[row] - rowpref[row];
+        }
+        const int idx = row_base + f;
+        x = p.x[idx];
+        y = p.y[idx];
+        z = p.z[idx];
+        ux = p.ux[idx];
+        uy = p.uy[idx];
+        uz = (float)p.uz[idx];
+        qw = p.w[idx];
+      }
+      const bool cold = __ballot(valid && (ux != 0.f || uy != 0.f || uz != 0.f)) == 0;
+      const float ginv = 1.f / sqrtf(1.f + ux * ux + uy * uy + uz * uz);
+      const float vx = ux * ginv, vy = uy * ginv, vz = uz * ginv;
+      // rho^{n+1} at x^{n+1} (and rho^n when the whole wave is at rest)
+      {
+        const ShapePos s = shape_at(x, y, z, zmin, g);
+        const uint32_t key = valid ? pos_key(s, g.nr) : A1.key;
+        float v[RS::K];
+        RS::values(valid ? qw : 0.f, s.eith, v);
+        acc_step<TR, H, RS::K, RS>(lds, A1, key, v, s, g, J0, C0, [](int k) { return RS::off(4, k); });
+        if (cold) {
+          const uint32_t key0 = valid ? key : An.key;
+          acc_step<TR, H, RS::K, RS>(lds, An, key0, v, s, g, J0, C0, [](int k) { return RS::off(3, k); });
+          continue;
+        }
+      }
+      // J^{n+1/2} at x^{n+1/2} = x^{n+1} - dt v / 2
+      {
+        const ShapePos s = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy,
+                                    z - 0.5 * dt * (double)vz, zmin, g);
+        const uint32_t key = valid ? pos_key(s, g.nr) : AJ.key;
+        float v[JS::K];
+        JS::values(valid ? qw : 0.f, vx, vy, vz, s.eith, v);
+        acc_step<TR, H, JS::K, JS>(lds, AJ, key, v, s, g, J0, C0, [](int k) { return JS::off(k); });
+      }
+      // rho^n at x^n = x^{n+1} - dt v
+      {
+        const ShapePos s = shape_at(x - dt * (double)vx, y - dt * (double)vy, z - dt * (double)vz, zmin, g);
+        const uint32_t key = valid ? pos_key(s, g.nr) : An.key;
+        float v[RS::K];
+        RS::values(valid ? qw : 0.f, s.eith, v);
+        acc_step<TR, H, RS::K, RS>(lds, An, key, v, s, g, J0, C0, [](int k) { return RS::off(3, k); });
       }
     }
-    // J^{n+1/2} at x^{n+1/2} = x^{n+1} - dt v / 2
-    {
-      const ShapePos s = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy,
-                                  z - 0.5 * dt * (double)vz, zmin, g);
-      const RunMask rm = run_mask(valid ? pos_key(s, g.nr) : kInvalidKey);
-      const Local<TR, H> L = localize<TR, H>(s, g, J0, C0);
-      float v[JS::K];
-      JS::values(qw, vx, vy, vz, s.eith, v);
-      deposit_set<JS::K, JS>(lds, v, valid, rm, s, L.na, L.nb, L.sa_even, L.sa_odd, L.sb,
-                             [](int k) { return JS::off(k); });
-    }
-    // rho^n at x^n = x^{n+1} - dt v
-    {
-      const ShapePos s = shape_at(x - dt * (double)vx, y - dt * (double)vy, z - dt * (double)vz, zmin, g);
-      const RunMask rm = run_mask(valid ? pos_key(s, g.nr) : kInvalidKey);
-      const Local<TR, H> L = localize<TR, H>(s, g, J0, C0);
-      float v[RS::K];
-      RS::values(qw, s.eith, v);
-      deposit_set<RS::K, RS>(lds, v, valid, rm, s, L.na, L.nb, L.sa_even, L.sa_odd, L.sb,
-                             [](int k) { return RS::off(3, k); });
-    }
   }
+  if (A1.key != kInvalidKey) acc_flush<TR, H, RS::K, RS>(lds, A1, g, J0, C0, [](int k) { return RS::off(4, k); });
+  if (An.key != kInvalidKey) acc_flush<TR, H, RS::K, RS>(lds, An, g, J0, C0, [](int k) { return RS::off(3, k); });
+  if (AJ.key != kInvalidKey) acc_flush<TR, H, JS::K, JS>(lds, AJ, g, J0, C0, [](int k) { return JS::off(k); });
   __syncthreads();
-  float2* dst = scratch + (size_t)b * nacc;
-  for (int e = tid; e < nacc; e += blockDim.x) dst[e] = lds_blk[e];
+  float* dst = scratch + (size_t)b * nacc;
+  for (int e = tid; e < nacc; e += blockDim.x) dst[e] = (float)lds[e];
 }
 
 // Node-parallel sum of every block slot covering the node, then: J-,0 =
@@ -417,20 +415,19 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
 template <int TR, int H, int M>
 __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__ nchunk,
                                                          const int* __restrict__ chunk_start,
-                                                         const float2* __restrict__ scratch,
+                                                         const float* __restrict__ scratch,
                                                          float2* __restrict__ real, const float2* __restrict__ bg,
                                                          Grid g, TileGeom tg) {
   using B = Blk<TR, H>;
-  constexpr int nacc = 5 * M * B::NODES;
+  constexpr int NV = Vals<M>::N;
+  constexpr int nacc = NV * B::NODES;
   const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int nz = g.nz, nr = g.nr;
   if (node >= (int64_t)nr * nz) return;
   const int i = (int)(node / nz), j = (int)(node % nz);
-  float2 acc[5][M];
+  float acc[NV];
 #pragma unroll
-  for (int sl = 0; sl < 5; ++sl)
-#pragma unroll
-    for (int m = 0; m < M; ++m) acc[sl][m] = make_float2(0.f, 0.f);
+  for (int v = 0; v < NV; ++v) acc[v] = 0.f;
   // covering tiles: bz = j - (J0 - H) mod nz in [0, BZ); br = i - (C0 - 1 - H) in [0, BR)
   const int tz0 = j / kTZ;
   const int tr0 = (i + 1) / TR;
@@ -451,23 +448,33 @@ __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__
       if (br < 0 || br >= B::BR) continue;
       const int t = tr * tg.ntz + tz;
       const int nch = nchunk[t];
-      const float2* blk = scratch + (size_t)chunk_start[t] * nacc + br * B::BZ + bz;
+      const float* blk = scratch + (size_t)chunk_start[t] * nacc + br * B::BZ + bz;
       for (int c = 0; c < nch; ++c) {
-        const float2* q = blk + (size_t)c * nacc;
+        const float* q = blk + (size_t)c * nacc;
 #pragma unroll
-        for (int sl = 0; sl < 5; ++sl)
-#pragma unroll
-          for (int m = 0; m < M; ++m) acc[sl][m] = cadd(acc[sl][m], q[(sl * M + m) * B::NODES]);
+        for (int v = 0; v < NV; ++v) acc[v] += q[v * B::NODES];
       }
     }
   }
-  acc[1][0] = cconj(acc[0][0]);
   const float inv_v = (float)(1.0 / (2.0 * M_PI * g.dr * g.dr * g.dz * (i + 0.5)));
+  // slot order of the grid: J+, J-, Jz, rho^n, rho^{n+1}
+  float2 out[5][M];
+  out[0][0] = make_float2(acc[0], acc[1]);
+  out[1][0] = make_float2(acc[0], -acc[1]);
+  out[2][0] = make_float2(acc[2], 0.f);
+  out[3][0] = make_float2(acc[3], 0.f);
+  out[4][0] = make_float2(acc[4], 0.f);
+#pragma unroll
+  for (int m = 1; m < M; ++m) {
+    const int b0 = vbase(m);
+#pragma unroll
+    for (int sl = 0; sl < 5; ++sl) out[sl][m] = make_float2(acc[b0 + 2 * sl], acc[b0 + 2 * sl + 1]);
+  }
 #pragma unroll
   for (int sl = 0; sl < 5; ++sl)
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      float2 v = cscale(acc[sl][m], inv_v);
+      float2 v = cscale(out[sl][m], inv_v);
       if (bg && sl >= 3) v = cadd(v, bg[(size_t)m * nr * nz + node]);
       real[dfidx(kCompJ + sl, m, M, nr, nz) + node] = v;
     }
@@ -486,41 +493,57 @@ DepositShape deposit_shape(int nz, int nr, int nmodes, int halo, int64_t cap) {
   d.ntiles = d.ntz * d.ntr;
   d.max_items = d.ntiles + (int)((cap + kChunk - 1) / kChunk);
   const int bz = d.TZ + 2 * halo + 1, br = d.TR + 2 * halo + 1;
-  d.acc_floats2 = (size_t)5 * nmodes * bz * br;
+  const int nv = 5 + 10 * (nmodes - 1);
+  d.acc_floats2 = ((size_t)nv * bz * br + 1) / 2;     // FP32 scratch slot per work item
+  d.lds_bytes = (size_t)nv * bz * br * sizeof(double);
   return d;
 }
 
 template <int TR, int H, int M>
 static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chunk_start, float2* scratch,
                        float2* real, const float2* bg, const Grid& g, const DepositShape& d, DevState* st,
-                       hipStream_t s) {
+                       int stages, hipStream_t s) {
   TileGeom tg{d.ntz, d.ntr, d.ntiles};
-  const size_t lds = (size_t)5 * M * Blk<TR, H>::NODES * sizeof(float2);
-  hipLaunchKernelGGL((k_tile_totals<TR>), dim3((d.ntiles + 3) / 4), dim3(256), 0, s, offset, g, tg, nchunk);
-  hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(1024), 0, s, nchunk, d.ntiles, chunk_start);
-  hipLaunchKernelGGL((k_deposit<TR, H, M>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk, chunk_start,
-                     scratch, g, tg, st);
-  const int64_t nodes = (int64_t)g.nr * g.nz;
-  hipLaunchKernelGGL((k_deposit_combine<TR, H, M>), dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, s, nchunk,
-                     chunk_start, scratch, real, bg, g, tg);
+  const size_t lds = (size_t)Vals<M>::N * Blk<TR, H>::NODES * sizeof(double);
+  if (stages & kDepPlan) {
+    hipLaunchKernelGGL((k_tile_totals<TR>), dim3((d.ntiles + 3) / 4), dim3(256), 0, s, offset, g, tg, nchunk);
+    hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(1024), 0, s, nchunk, d.ntiles, chunk_start);
+  }
+  if (stages & kDepTiles) {
+    static bool attr_set = false;   // dynamic LDS above the default limit
+    if (!attr_set) {
+      if (hipFuncSetAttribute((const void*)k_deposit<TR, H, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds) != hipSuccess)
+        return;   // the error stays pending and is reported by the caller's launch check
+      attr_set = true;
+    }
+    hipLaunchKernelGGL((k_deposit<TR, H, M>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk, chunk_start,
+                       (float*)scratch, g, tg, st);
+  }
+  if (stages & kDepCombine) {
+    const int64_t nodes = (int64_t)g.nr * g.nz;
+    hipLaunchKernelGGL((k_deposit_combine<TR, H, M>), dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, s,
+                       nchunk, chunk_start, (const float*)scratch, real, bg, g, tg);
+  }
 }
 
 template <int H>
 static void launch_dep_h(const Parts& p, const int* offset, int* nchunk, int* chunk_start, float2* scratch,
                          float2* real, const float2* bg, const Grid& g, const DepositShape& d, DevState* st,
-                         hipStream_t s) {
+                         int stages, hipStream_t s) {
   switch (g.nmodes) {
-    case 1: launch_dep<16, H, 1>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, s); break;
-    case 2: launch_dep<16, H, 2>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, s); break;
-    case 3: launch_dep<8, H, 3>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, s); break;
-    default: launch_dep<8, H, 4>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, s); break;
+    case 1: launch_dep<16, H, 1>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
+    case 2: launch_dep<16, H, 2>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
+    case 3: launch_dep<8, H, 3>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
+    default: launch_dep<8, H, 4>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
   }
 }
 
 void launch_deposit(const Parts& p, const int* offset, const DepositShape& d, int* nchunk, int* chunk_start,
-                    float2* scratch, float2* real, const float2* bg, const Grid& g, DevState* st, hipStream_t s) {
-  if (d.halo == 1) launch_dep_h<1>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, s);
-  else launch_dep_h<2>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, s);
+                    float2* scratch, float2* real, const float2* bg, const Grid& g, DevState* st, int stages,
+                    hipStream_t s) {
+  if (d.halo == 1) launch_dep_h<1>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s);
+  else launch_dep_h<2>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s);
 }
 
 }  // namespace pic

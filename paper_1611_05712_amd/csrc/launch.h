@@ -50,11 +50,15 @@ struct DepositShape {
   int TZ, TR, ntz, ntr, ntiles;
   int halo;             // cells a particle can move per step (1 or 2)
   int max_items;        // workgroups launched (upper bound of the work list)
-  size_t acc_floats2;   // complex accumulators per block (tile + halo nodes)
+  size_t acc_floats2;   // FP32 scratch slot per work item, in float2 units (values x block nodes)
+  size_t lds_bytes;     // FP64 LDS block of one workgroup
 };
 DepositShape deposit_shape(int nz, int nr, int nmodes, int halo, int64_t cap);
+// stages of the deposit: work-list planning, tile accumulation, node combine
+constexpr int kDepPlan = 1, kDepTiles = 2, kDepCombine = 4, kDepAll = 7;
 void launch_deposit(const Parts& p, const int* offset, const DepositShape& d, int* nchunk, int* chunk_start,
-                    float2* partial, float2* real, const float2* bg, const Grid& g, DevState* st, hipStream_t s);
+                    float2* scratch, float2* real, const float2* bg, const Grid& g, DevState* st, int stages,
+                    hipStream_t s);
 void launch_inject(const Parts& p, DevState* st, const Grid& g, const InjectTable& tab, int cap, hipStream_t s);
 void launch_uniform_check(const float2* rho, int rows, int nz, unsigned int* out, hipStream_t s);
 

@@ -162,31 +162,35 @@ __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __re
       k = (uint32_t)g.ncells;
     } else {
       double x = p.x[i], y = p.y[i];
-      float ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
+      float ux = p.ux[i], uy = p.uy[i];
+      double uz = p.uz[i];
       float qm = sc.qm[p.sp[i]];
       ShapePos s = shape_at(x, y, z, zmin, g);
       float Ex, Ey, Ez, Bx, By, Bz;
       gather_eb<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
-      // Boris rotation (J. P. Boris, 1970)
+      // Boris rotation (J. P. Boris, 1970).  The transverse momenta and all
+      // increments are FP32; u_z accumulates its increments in FP64.
       float eps = qm * (float)g.dt * 0.5f;
-      float umx = ux + eps * Ex, umy = uy + eps * Ey, umz = uz + eps * Ez;
-      float gm = sqrtf(1.f + umx * umx + umy * umy + umz * umz);
+      float umx = ux + eps * Ex, umy = uy + eps * Ey;
+      double umz = uz + (double)(eps * Ez);
+      float fmz = (float)umz;
+      float gm = sqrtf(1.f + umx * umx + umy * umy + fmz * fmz);
       float tx = eps * Bx / gm, ty = eps * By / gm, tz = eps * Bz / gm;
       float sfac = 2.f / (1.f + tx * tx + ty * ty + tz * tz);
       float sx = sfac * tx, sy = sfac * ty, sz = sfac * tz;
-      float upx = umx + (umy * tz - umz * ty);
-      float upy = umy + (umz * tx - umx * tz);
-      float upz = umz + (umx * ty - umy * tx);
+      float dpz = umx * ty - umy * tx;
+      float upx = umx + (umy * tz - fmz * ty);
+      float upy = umy + (fmz * tx - umx * tz);
+      float upz = (float)(umz + (double)dpz);
       float uqx = umx + (upy * sz - upz * sy);
       float uqy = umy + (upz * sx - upx * sz);
-      float uqz = umz + (upx * sy - upy * sx);
       ux = uqx + eps * Ex;
       uy = uqy + eps * Ey;
-      uz = uqz + eps * Ez;
-      float ginv = 1.f / sqrtf(1.f + ux * ux + uy * uy + uz * uz);
-      x += g.dt * (double)(ux * ginv);
-      y += g.dt * (double)(uy * ginv);
-      z += g.dt * (double)(uz * ginv);
+      uz = umz + (double)(upx * sy - upy * sx) + (double)(eps * Ez);
+      double ginv = 1.0 / sqrt(1.0 + (double)ux * ux + (double)uy * uy + uz * uz);
+      x += g.dt * ((double)ux * ginv);
+      y += g.dt * ((double)uy * ginv);
+      z += g.dt * (uz * ginv);
       p.x[i] = x;
       p.y[i] = y;
       p.z[i] = z;
@@ -300,8 +304,8 @@ __global__ __launch_bounds__(256) void k_scan_apply(int* __restrict__ count, int
 // as one contiguous run even when the wake has scrambled the input order.
 // --------------------------------------------------------------------------
 struct PartRec {
-  double x, y, z;
-  float ux, uy, uz, w;
+  double x, y, z, uz;
+  float ux, uy, w;
   uint32_t sp;
 };
 
@@ -412,7 +416,7 @@ __global__ __launch_bounds__(256) void k_inject(Parts p, DevState* st, Grid g, I
   p.z[d] = z;
   p.ux[d] = 0.f;
   p.uy[d] = 0.f;
-  p.uz[d] = 0.f;
+  p.uz[d] = 0.0;
   p.w[d] = (float)(tab.q[sidx] * (double)wf);
   p.sp[d] = (uint8_t)tab.sp[sidx];
 }

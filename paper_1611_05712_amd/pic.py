@@ -28,7 +28,7 @@ EXPORTED = (
     "pic_fft_z", "pic_dht_gemm", "pic_timing_enable", "pic_timing_read",
 )
 TIMERS = ("gather_push", "sort", "deposit", "fft_fwd", "dht_fwd", "psatd", "dht_inv", "fft_inv",
-          "window")
+          "window", "scan", "dep_plan", "dep_combine", "pack")
 
 
 class PicError(RuntimeError):
@@ -96,7 +96,7 @@ def load(path: str = LIB_PATH):
     L.pic_get_field.argtypes = [vp, i32, i32, i32, vp]
     L.pic_set_field.argtypes = [vp, i32, i32, vp]
     L.pic_num_particles.argtypes = [vp, ctypes.POINTER(i64)]
-    L.pic_get_particles.argtypes = [vp, i32, i64, _dp, _fp, _fp, ctypes.POINTER(i64)]
+    L.pic_get_particles.argtypes = [vp, i32, i64, _dp, _dp, _fp, ctypes.POINTER(i64)]
     L.pic_get_state.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     L.pic_strerror.argtypes = [i32]
     L.pic_strerror.restype = ctypes.c_char_p
@@ -227,11 +227,11 @@ class Simulation:
         if cap is None:
             cap = self.num_particles()
         xyz = np.empty((cap, 3), np.float64)
-        uvw = np.empty((cap, 3), np.float32)
+        uvw = np.empty((cap, 3), np.float64)
         w = np.empty(cap, np.float32)
         n = ctypes.c_int64()
         _check(self._L.pic_get_particles(self._ctx, k, cap, xyz.ctypes.data_as(_dp),
-                                         uvw.ctypes.data_as(_fp), w.ctypes.data_as(_fp),
+                                         uvw.ctypes.data_as(_dp), w.ctypes.data_as(_fp),
                                          ctypes.byref(n)), "pic_get_particles")
         m = n.value
         return {"x": xyz[:m, 0], "y": xyz[:m, 1], "z": xyz[:m, 2], "ux": uvw[:m, 0],

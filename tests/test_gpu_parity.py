@@ -261,3 +261,59 @@ def test_full_cycle_small_ten_steps_beam_moments():
     for k in ("z_mean", "sigma_z", "mean_gamma", "sigma_gamma", "eps_nx", "eps_ny"):
         assert got[k] == pytest.approx(want[k], rel=1e-4, abs=1e-4 * floors.get(k, 0.0)), k
     assert sim.num_particles() == sum(x.x.size for x in o.species if x.mobile)
+
+
+def _vector_rel(sim, o, m, which):
+    """relative L2 of the mode-m vector field E or B (its +, -, z components)"""
+    off = 0 if which == "E" else 3
+    ref = (o.E if which == "E" else o.B)[m]
+    got = np.stack([sim.get_field(m, COMPS[off + c]) for c in range(3)])
+    return _rel(got, ref)
+
+
+def test_c0_one_step_fields():
+    """256 x 64, p = 16 beam-plasma workload, one full cycle: each mode's E and B
+    within relative L2 1e-5 of the oracle.  (The small radial components of
+    mode 0 alone sit near 1e-5: FP32 rounding of the order-one electron density
+    against the ion background sets their floor.)"""
+    wl = preset("c0")
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.step(1)
+    o.step(1)
+    for m in range(2):
+        for which in ("E", "B"):
+            assert _vector_rel(sim, o, m, which) < FIELD_TOL, (m, which)
+
+
+def test_c0_fifty_steps_against_stored_oracle_run():
+    """The same workload for 50 steps: drive moments after 1, 10, 25 and 50
+    steps within relative 1e-4, field norms within 1e-4, live particle count
+    exact.  Expected values: tests/golden/c0_oracle.json (oracle only)."""
+    import json
+    import os
+    rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c0_oracle.json")))
+    wl = preset(rec["workload"], seed=rec["seed"])
+    sim = _sim(wl)
+    final = rec["steps"]["50"]["drive"]
+    # quantities that start at zero for the cold beam get an absolute floor of
+    # 1e-4 times their value at the end of the run
+    floors = {k: final[k] for k in ("eps_nx", "eps_ny", "sigma_gamma", "mean_slice_sigma_gamma")}
+    done = 0
+    for n in (1, 10, 25, 50):
+        sim.step(n - done)
+        done = n
+        e = rec["steps"][str(n)]
+        assert sim.num_particles() == e["n_mobile"], n
+        got = sim.diagnostics("drive", slice_len=0.02975)
+        want = e["drive"]
+        assert got["n"] == want["n"] and got["n_slices"] == want["n_slices"], n
+        for k in ("z_mean", "sigma_z", "mean_gamma", "eps_nx", "eps_ny", "sigma_gamma",
+                  "mean_slice_sigma_gamma"):
+            assert got[k] == pytest.approx(want[k], rel=1e-4, abs=1e-4 * floors.get(k, 0.0)), (n, k)
+        for m in range(2):
+            for which in ("E", "B"):
+                names = COMPS[:3] if which == "E" else COMPS[3:]
+                g = np.sqrt(sum(np.linalg.norm(sim.get_field(m, cn)) ** 2 for cn in names))
+                w = np.sqrt(sum(e["field_norm"][f"{m}:{cn}"] ** 2 for cn in names))
+                assert g == pytest.approx(w, rel=1e-4, abs=1e-12), (n, m, which)
