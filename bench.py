@@ -6,8 +6,12 @@
 A step is one whole PIC cycle (gather + Boris push, cell sort, tile deposit,
 forward z-FFT + Hankel transform, current correction + PSATD, inverse
 transforms, moving window with injection) over the synthetic beam-plasma
-workload, everything resident in HBM.  W untimed steps (to reach the blown-out
-wake) are followed by K timed steps.  One JSON line is printed:
+workload, everything resident in HBM.  W untimed steps are followed by K
+timed steps; the default W = 1500 puts the timed steps in the steady state of
+the 2000-step run, where the wake behind the drive fills the window (the
+moving window brings fresh cold plasma in at the head, and before ~1400 steps
+part of the box still holds plasma the beam never crossed).  One JSON line is
+printed:
 
   value       = mobile macro-particles x K / wall time  (particle-pushes/s)
   roofline    = the kernel with the largest GPU time, its algorithmic bytes
@@ -33,9 +37,10 @@ MFMA_BF16_TFLOPS = 2500.0      # dense bf16 / fp16
 
 # algorithmic traffic per unit of work (bytes), see the design doc
 BYTES_PER_PARTICLE = {
-    "gather_push": 78.0,   # read x,y,z (24) + u (12); write 36; field share ~6
-    "sort": 86.0,          # scatter: read key (4) + particle (41); write particle (41)
-    "deposit": 45.0,       # read x,y,z (24) + u (12) + w (4); grid share ~5
+    # particle record: x, y, z, u_z FP64 (32) + u_x, u_y, q*w FP32 (12) + species (1) = 45 B
+    "gather_push": 91.0,   # read x,y,z,u (40) + species (1); write x,y,z,u (40) + key (4); field share ~6
+    "sort": 94.0,          # scatter: read key (4) + record (45); write record (45)
+    "deposit": 49.0,       # read x,y,z,u (40) + q*w (4); grid share ~5
 }
 BYTES_PER_CELL = {
     "fft_fwd": 16.0,       # read + write one complex64 per cell and transform
@@ -136,10 +141,13 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=1500)
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--hankel-prec", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run 5 device-to-device copies of BYTES (scale of the rocprofv3 "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -149,6 +157,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "launches": 5}))
+        return
     from paper_1611_05712_amd import Simulation
     from workloads import preset
 

@@ -6,27 +6,31 @@
 //     TZ x TR tiles and each particle belongs to exactly one tile;
 //   * a tile's particles touch the nodes of its cells plus a halo of H cells
 //     (x^n, x^{n+1/2} lie within dt c of x^{n+1}, dt <= H dz and H dr), so
-//     a workgroup accumulates a (TZ + 2H + 1) x (TR + 2H + 1) node block in LDS
-//     and writes it to a scratch slot;
-//   * dense tiles (beam cores hold thousands of particles per cell) are cut
-//     into chunks of at most kChunk particles, each with its own slot; the
-//     device builds this work list (k_tile_plan) from the sorted offsets;
-//   * k_deposit_combine sums, node by node, the slots of every block covering
+//     a workgroup accumulates a (TZ + 2H + 1) x (TR + 2H + 1) node block in
+//     LDS (FP64: on gfx950 an FP64 LDS atomic is ~20x cheaper than an FP32
+//     one) and writes it to an FP32 scratch slot;
+//   * dense tiles (beam cores and compressed plasma, more than kTileMax
+//     particles) are cut into chunks of kChunk particles, each its own
+//     workgroup and slot; the device builds this work list (k_tile_plan) from
+//     the sorted offsets, and k_chunk_reduce sums a tile's chunk slots into
+//     its first one;
+//   * k_deposit_combine sums, node by node, the slots of the tiles covering
 //     the node and writes the grid.
-// Within a workgroup every lane takes short runs of consecutive cell-sorted
-// particles.  Particles of one cell share their four nodes, so a lane sums
-// the node contributions of each of the three positions in registers and
-// issues the LDS atomics only when that position's cell changes (and once at
-// the end).  Beam cores with thousands of particles per cell then cost one
-// flush per lane rather than one atomic per particle, and neighbouring lanes'
-// flushes rarely hit the same node.  Waves whose particles are all at rest skip the current and
-// reuse the x^{n+1} shape for rho^n.
+// Within a workgroup every lane takes runs of at most kRun particles of one
+// cell.  Particles of one cell share their four nodes, so a lane sums the node
+// contributions of each of the three positions in registers and issues the
+// LDS atomics only when that position's cell changes; for x^{n+1} that is at
+// most once per run, for all lanes together.  Beam cores with thousands of
+// particles per cell cost one flush per run rather than one atomic per
+// particle.  Waves whose particles are all at rest skip the current and reuse
+// the x^{n+1} shape for rho^n.
 #include "common.h"
 #include "launch.h"
 
 namespace pic {
 
-constexpr int kChunk = 16384;   // max particles per workgroup
+constexpr int kTileMax = 12288;  // a tile with more particles than this is cut into chunks
+constexpr int kChunk = 4096;     // particles per chunk of a dense tile
 constexpr int kTZ = 32;
 constexpr int kRun = 8;       // consecutive particles per lane per sub-chunk
 
@@ -62,7 +66,7 @@ __global__ __launch_bounds__(256) void k_tile_totals(const int* __restrict__ off
     s = offset[j * g.ncol + C1] - offset[j * g.ncol + C0];
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) nchunk[t] = s > 0 ? (s + kChunk - 1) / kChunk : 1;
+  if (lane == 0) nchunk[t] = s > kTileMax ? (s + kChunk - 1) / kChunk : 1;
 }
 
 // exclusive scan of chunk counts: chunk_start[0..ntiles], chunk_start[ntiles] = work items
@@ -204,7 +208,9 @@ __device__ __forceinline__ uint32_t pos_key(const ShapePos& s, int nr) {
 }
 
 // Register accumulator of one position kind: the cell key it belongs to and
-// the K values times the four node weights (ia,j0), (ia,j0+1), (ib,j0), (ib,j0+1).
+// the K values times the four node weights (ia,j0), (ia,j0+1), (ib,j0),
+// (ib,j0+1).  A run adds at most a few particles before it is flushed into
+// the FP64 block.
 template <int K>
 struct Acc {
   uint32_t key;
@@ -249,12 +255,12 @@ __device__ __forceinline__ void acc_flush(double* __restrict__ lds, const Acc<K>
   }
   if (L.sa_even != 0.f) {
     double* pa = lds + L.na;
+    const float sg = L.sa_odd;   // -1 on the ghost node across the axis (odd Hankel orders)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float sa = Set::parity(k) ? L.sa_odd : L.sa_even;
       const int o = off(k);
-      atomicAdd(pa + o, (double)(sa * A.a[4 * k + 0]));
-      atomicAdd(pa + o + 1, (double)(sa * A.a[4 * k + 1]));
+      atomicAdd(pa + o, (double)(Set::parity(k) ? sg * A.a[4 * k + 0] : A.a[4 * k + 0]));
+      atomicAdd(pa + o + 1, (double)(Set::parity(k) ? sg * A.a[4 * k + 1] : A.a[4 * k + 1]));
     }
   }
 }
@@ -271,6 +277,21 @@ __device__ __forceinline__ void acc_step(double* __restrict__ lds, Acc<K>& A, ui
   acc_add(A, v, s.fz, s.fr);
 }
 
+// one particle's deposit inputs
+struct PLoad {
+  double x = 0.0, y = 0.0, z = 0.0, uz = 0.0;
+  float ux = 0.f, uy = 0.f, w = 0.f;
+  __device__ __forceinline__ void load(const Parts& p, int i) {
+    x = p.x[i];
+    y = p.y[i];
+    z = p.z[i];
+    uz = p.uz[i];
+    ux = p.ux[i];
+    uy = p.uy[i];
+    w = p.w[i];
+  }
+};
+
 template <int TR, int H, int M>
 __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict__ offset,
                                                  const int* __restrict__ nchunk, const int* __restrict__ chunk_start,
@@ -279,8 +300,11 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
   using RS = RhoSet<M, B::NODES>;
   using JS = JSet<M, B::NODES>;
   extern __shared__ double lds[];
+  constexpr int kCells = kTZ * TR;              // cells (key columns x rows) of a tile
   __shared__ int rowstart[kTZ];
   __shared__ int rowpref[kTZ + 1];
+  __shared__ uint16_t runpref[kCells + 1];      // runs of <= kRun particles before each cell
+  __shared__ int wsum[4];
   __shared__ int s_tile;
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
@@ -318,64 +342,118 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
   }
   __syncthreads();
   const int total = rowpref[kTZ];
-  const int f0 = chunk * kChunk;
-  const int f1 = min(total, f0 + kChunk);
+  const bool whole = nchunk[t] == 1;
+  const int f0 = whole ? 0 : chunk * kChunk;
+  const int f1 = whole ? total : min(total, f0 + kChunk);
   const double zmin = st->zmin;
   const double dt = g.dt;
+  // Runs: every cell's particles (clipped to this chunk) are cut into runs of
+  // at most kRun, so a run never leaves its cell of x^{n+1}.  runpref is the
+  // exclusive prefix of the run counts over the tile's cells.
+  auto cell_range = [&](int c, int& lo, int& hi) {
+    const int row = c / TR, col = c % TR;
+    lo = hi = 0;
+    if (C0 + col < C1) {
+      const int* o = offset + (J0 + row) * g.ncol + C0 + col;
+      lo = max(f0, rowpref[row] + (o[0] - rowstart[row]));
+      hi = min(f1, rowpref[row] + (o[1] - rowstart[row]));
+    }
+  };
+  {
+    static_assert(kCells % 256 == 0 && kCells <= 512, "tile cells per thread");
+    constexpr int per = kCells / 256;
+    int nrun[per], tot = 0;
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+      int lo, hi;
+      cell_range(tid * per + q, lo, hi);
+      nrun[q] = hi > lo ? (hi - lo + kRun - 1) / kRun : 0;
+      tot += nrun[q];
+    }
+    // block-wide exclusive scan of the per-thread totals
+    const int lane = tid & 63, wave = tid >> 6;
+    int inc = tot;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += u;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    int excl = inc - tot;
+    for (int w = 0; w < wave; ++w) excl += wsum[w];
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+      runpref[tid * per + q] = (uint16_t)excl;
+      excl += nrun[q];
+    }
+    if (tid == 255) runpref[kCells] = (uint16_t)excl;
+    __syncthreads();
+  }
+  const int nruns = runpref[kCells];
   Acc<RS::K> An, A1;
   Acc<JS::K> AJ;
   acc_reset(An, kInvalidKey);
   acc_reset(A1, kInvalidKey);
   acc_reset(AJ, kInvalidKey);
-  // The chunk is walked in sub-chunks of 256 * kRun particles; in each, lane
-  // tid takes the kRun consecutive particles from tid * kRun.  A sub-chunk's
-  // particle data stays cache resident while its lanes consume it, and a lane
-  // keeps its accumulators across sub-chunks (long runs of one cell in dense
-  // beams flush once).
-  for (int sb = f0; sb < f1; sb += 256 * kRun) {
-    int f = sb + tid * kRun;
-    const int fe = min(f + kRun, f1);
-    int row = 0, row_end = 0, row_base = 0;
-    if (f < fe) {
-      int lo = 0, hi = kTZ;   // rowpref[lo] <= f < rowpref[hi]
+  // Round r0: thread tid takes run r0 + tid.  All lanes start their runs
+  // together, so the rho^{n+1} accumulator (whose cell is the run's cell)
+  // flushes at most once per round; rho^n and J flush when their own cell
+  // changes.  A lane keeps its accumulators across rounds (a beam cell with
+  // thousands of particles gives one lane consecutive runs of one cell).
+  for (int r0 = 0; r0 < nruns; r0 += 256) {
+    const int r = r0 + tid;
+    int len = 0, idx0 = 0;
+    uint32_t rkey = A1.key;
+    if (r < nruns) {
+      int lo = 0, hi = kCells;   // runpref[lo] <= r < runpref[hi]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (rowpref[mid] <= f) lo = mid;
+        if ((int)runpref[mid] <= r) lo = mid;
         else hi = mid;
       }
-      row = lo;
-      row_end = rowpref[lo + 1];
-      row_base = rowstart[lo] - rowpref[lo];
+      int a, e;
+      cell_range(lo, a, e);
+      const int start = a + (r - (int)runpref[lo]) * kRun;
+      len = min(kRun, e - start);
+      const int row = lo / TR, col = lo % TR;
+      idx0 = rowstart[row] + (start - rowpref[row]);
+      rkey = (uint32_t)(J0 + row) * 2048u + (uint32_t)(C0 + col);
     }
-    for (int it = 0; it < kRun; ++it, ++f) {
-      const bool valid = f < fe;
+    if (rkey != A1.key) {
+      if (A1.key != kInvalidKey) acc_flush<TR, H, RS::K, RS>(lds, A1, g, J0, C0, [](int k) { return RS::off(4, k); });
+      acc_reset(A1, rkey);
+    }
+    // particle data of the next iteration is loaded before the current one
+    // is processed, so its latency overlaps the arithmetic
+    PLoad nx;
+    if (len > 0) nx.load(p, idx0);
+    for (int it = 0; it < kRun; ++it) {
+      const bool valid = it < len;
+      const PLoad cur = nx;
+      if (it + 1 < len) nx.load(p, idx0 + it + 1);
       double x = 0.0, y = 0.0, z = zmin;
       float ux = 0.f, uy = 0.f, uz = 0.f, qw = 0.f;
       if (valid) {
-        while (f >= row_end) {   // skips empty rows; row < kTZ - 1 here since f < total
-          ++row;
-          row_end = rowpref[row + 1];
-          row_base = rowstart[row] - rowpref[row];
-        }
-        const int idx = row_base + f;
-        x = p.x[idx];
-        y = p.y[idx];
-        z = p.z[idx];
-        ux = p.ux[idx];
-        uy = p.uy[idx];
-        uz = (float)p.uz[idx];
-        qw = p.w[idx];
+        x = cur.x;
+        y = cur.y;
+        z = cur.z;
+        ux = cur.ux;
+        uy = cur.uy;
+        uz = (float)cur.uz;
+        qw = cur.w;
       }
       const bool cold = __ballot(valid && (ux != 0.f || uy != 0.f || uz != 0.f)) == 0;
       const float ginv = 1.f / sqrtf(1.f + ux * ux + uy * uy + uz * uz);
       const float vx = ux * ginv, vy = uy * ginv, vz = uz * ginv;
-      // rho^{n+1} at x^{n+1} (and rho^n when the whole wave is at rest)
+      // rho^{n+1} at x^{n+1}, in the run's cell (particles beyond the last
+      // radial node share the last key column and deposit nothing); rho^n
+      // too when the whole wave is at rest
       {
         const ShapePos s = shape_at(x, y, z, zmin, g);
         const uint32_t key = valid ? pos_key(s, g.nr) : A1.key;
         float v[RS::K];
-        RS::values(valid ? qw : 0.f, s.eith, v);
-        acc_step<TR, H, RS::K, RS>(lds, A1, key, v, s, g, J0, C0, [](int k) { return RS::off(4, k); });
+        RS::values(valid && s.i0 < g.nr ? qw : 0.f, s.eith, v);
+        acc_add(A1, v, s.fz, s.fr);
         if (cold) {
           const uint32_t key0 = valid ? key : An.key;
           acc_step<TR, H, RS::K, RS>(lds, An, key0, v, s, g, J0, C0, [](int k) { return RS::off(3, k); });
@@ -409,12 +487,37 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
   for (int e = tid; e < nacc; e += blockDim.x) dst[e] = (float)lds[e];
 }
 
-// Node-parallel sum of every block slot covering the node, then: J-,0 =
+// Chunks of a dense tile: their blocks are summed into the tile's first slot
+// (grid: tiles x element blocks, one element per thread).
+template <int TR, int H, int M>
+__global__ __launch_bounds__(256) void k_chunk_reduce(const int* __restrict__ nchunk,
+                                                      const int* __restrict__ chunk_start, float* __restrict__ scratch,
+                                                      int ntiles) {
+  using B = Blk<TR, H>;
+  constexpr int nacc = Vals<M>::N * B::NODES;
+  const int t = blockIdx.x;
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  if (t >= ntiles || e >= nacc) return;
+  const int nch = nchunk[t];
+  if (nch <= 1) return;
+  float* base = scratch + (size_t)chunk_start[t] * nacc + e;
+  float a0 = base[0], a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  int c = 1;
+  for (; c + 3 < nch; c += 4) {
+    a0 += base[(size_t)c * nacc];
+    a1 += base[(size_t)(c + 1) * nacc];
+    a2 += base[(size_t)(c + 2) * nacc];
+    a3 += base[(size_t)(c + 3) * nacc];
+  }
+  for (; c < nch; ++c) a0 += base[(size_t)c * nacc];
+  base[0] = (a0 + a1) + (a2 + a3);
+}
+
+// Node-parallel sum of the tile blocks covering the node, then: J-,0 =
 // conj(J+,0), division by the ring volume 2 pi r_i dr dz, immobile background
 // added to both densities.
 template <int TR, int H, int M>
-__global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__ nchunk,
-                                                         const int* __restrict__ chunk_start,
+__global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__ chunk_start,
                                                          const float* __restrict__ scratch,
                                                          float2* __restrict__ real, const float2* __restrict__ bg,
                                                          Grid g, TileGeom tg) {
@@ -447,13 +550,9 @@ __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__
       const int br = i - (tr * TR - 1 - H);
       if (br < 0 || br >= B::BR) continue;
       const int t = tr * tg.ntz + tz;
-      const int nch = nchunk[t];
-      const float* blk = scratch + (size_t)chunk_start[t] * nacc + br * B::BZ + bz;
-      for (int c = 0; c < nch; ++c) {
-        const float* q = blk + (size_t)c * nacc;
+      const float* q = scratch + (size_t)chunk_start[t] * nacc + br * B::BZ + bz;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] += q[v * B::NODES];
-      }
+      for (int v = 0; v < NV; ++v) acc[v] += q[v * B::NODES];
     }
   }
   const float inv_v = (float)(1.0 / (2.0 * M_PI * g.dr * g.dr * g.dz * (i + 0.5)));
@@ -521,9 +620,12 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
                        (float*)scratch, g, tg, st);
   }
   if (stages & kDepCombine) {
+    constexpr int nacc = Vals<M>::N * Blk<TR, H>::NODES;
+    hipLaunchKernelGGL((k_chunk_reduce<TR, H, M>), dim3(d.ntiles, (nacc + 255) / 256), dim3(256), 0, s, nchunk,
+                       chunk_start, (float*)scratch, d.ntiles);
     const int64_t nodes = (int64_t)g.nr * g.nz;
     hipLaunchKernelGGL((k_deposit_combine<TR, H, M>), dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, s,
-                       nchunk, chunk_start, (const float*)scratch, real, bg, g, tg);
+                       chunk_start, (const float*)scratch, real, bg, g, tg);
   }
 }
 
