@@ -94,8 +94,9 @@ def _kernel_sources_hash():
 
 
 def _traffic(kernel, workload):
-    """HBM bytes per launch measured by rocprofv3 counters (profiles/traffic.json),
-    valid only while the kernel sources are unchanged."""
+    """HBM GB per launch measured by rocprofv3 FETCH_SIZE / WRITE_SIZE counters,
+    each scaled by what it reads for a device copy of known size
+    (profiles/traffic.json); None once the kernel sources have changed."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -106,7 +107,7 @@ def _traffic(kernel, workload):
     e = d.get(workload, {}).get(kernel)
     if not e or e.get("sources") != _kernel_sources_hash():
         return None
-    return e.get("bytes_per_launch")
+    return round(e["bytes_per_launch"] / 1e9, 4)
 
 
 def cpu_baseline(wl_name, stride=8):
