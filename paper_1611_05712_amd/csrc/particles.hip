@@ -145,63 +145,97 @@ __device__ __forceinline__ void gather_eb(const float2* __restrict__ gf, const S
 }
 
 // --------------------------------------------------------------------------
-// gather + Boris push + move + new cell key + key histogram
+// gather + Boris push + move + new cell key + key histogram.  Each thread
+// pushes kPushPer particles, blockDim apart: all their loads are issued before
+// any of them is computed, so a wave keeps twice the memory requests in
+// flight (the kernel waits on memory, not on arithmetic).
 // --------------------------------------------------------------------------
+constexpr int kPushPer = 2;
+
+struct PushRec {
+  double x, y, z, uz;
+  float ux, uy;
+  uint8_t sp;
+};
+
+template <int M>
+__device__ __forceinline__ uint32_t push_one(PushRec& r, const float2* __restrict__ gf, const Grid& g,
+                                             const SpeciesConst& sc, double zmin, bool kill) {
+  if (kill && r.z < zmin) return (uint32_t)g.ncells;
+  const float qm = sc.qm[r.sp];
+  ShapePos s = shape_at(r.x, r.y, r.z, zmin, g);
+  float Ex, Ey, Ez, Bx, By, Bz;
+  gather_eb<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
+  // Boris rotation (J. P. Boris, 1970).  The transverse momenta and all
+  // increments are FP32; u_z accumulates its increments in FP64.
+  float eps = qm * (float)g.dt * 0.5f;
+  float umx = r.ux + eps * Ex, umy = r.uy + eps * Ey;
+  double umz = r.uz + (double)(eps * Ez);
+  float fmz = (float)umz;
+  float gm = sqrtf(1.f + umx * umx + umy * umy + fmz * fmz);
+  float tx = eps * Bx / gm, ty = eps * By / gm, tz = eps * Bz / gm;
+  float sfac = 2.f / (1.f + tx * tx + ty * ty + tz * tz);
+  float sx = sfac * tx, sy = sfac * ty, sz = sfac * tz;
+  float dpz = umx * ty - umy * tx;
+  float upx = umx + (umy * tz - fmz * ty);
+  float upy = umy + (fmz * tx - umx * tz);
+  float upz = (float)(umz + (double)dpz);
+  float uqx = umx + (upy * sz - upz * sy);
+  float uqy = umy + (upz * sx - upx * sz);
+  r.ux = uqx + eps * Ex;
+  r.uy = uqy + eps * Ey;
+  r.uz = umz + (double)(upx * sy - upy * sx) + (double)(eps * Ez);
+  double ginv = 1.0 / sqrt(1.0 + (double)r.ux * r.ux + (double)r.uy * r.uy + r.uz * r.uz);
+  r.x += g.dt * ((double)r.ux * ginv);
+  r.y += g.dt * ((double)r.uy * ginv);
+  r.z += g.dt * (r.uz * ginv);
+  return cell_key(shape_at(r.x, r.y, r.z, zmin, g), g);
+}
+
 template <int M>
 __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __restrict__ gf, Grid g, SpeciesConst sc,
                                                      const DevState* __restrict__ st, uint32_t* __restrict__ key,
                                                      int* __restrict__ count) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int base = blockIdx.x * (kPushPer * 256) + threadIdx.x;
   const int n = st->n_part;
   const double zmin = st->zmin;
   const bool kill = g.moving_window && st->n_shift > 0;
-  uint32_t k = kInvalidKey;
-  if (i < n) {
-    double z = p.z[i];
-    if (kill && z < zmin) {
-      k = (uint32_t)g.ncells;
-    } else {
-      double x = p.x[i], y = p.y[i];
-      float ux = p.ux[i], uy = p.uy[i];
-      double uz = p.uz[i];
-      float qm = sc.qm[p.sp[i]];
-      ShapePos s = shape_at(x, y, z, zmin, g);
-      float Ex, Ey, Ez, Bx, By, Bz;
-      gather_eb<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
-      // Boris rotation (J. P. Boris, 1970).  The transverse momenta and all
-      // increments are FP32; u_z accumulates its increments in FP64.
-      float eps = qm * (float)g.dt * 0.5f;
-      float umx = ux + eps * Ex, umy = uy + eps * Ey;
-      double umz = uz + (double)(eps * Ez);
-      float fmz = (float)umz;
-      float gm = sqrtf(1.f + umx * umx + umy * umy + fmz * fmz);
-      float tx = eps * Bx / gm, ty = eps * By / gm, tz = eps * Bz / gm;
-      float sfac = 2.f / (1.f + tx * tx + ty * ty + tz * tz);
-      float sx = sfac * tx, sy = sfac * ty, sz = sfac * tz;
-      float dpz = umx * ty - umy * tx;
-      float upx = umx + (umy * tz - fmz * ty);
-      float upy = umy + (fmz * tx - umx * tz);
-      float upz = (float)(umz + (double)dpz);
-      float uqx = umx + (upy * sz - upz * sy);
-      float uqy = umy + (upz * sx - upx * sz);
-      ux = uqx + eps * Ex;
-      uy = uqy + eps * Ey;
-      uz = umz + (double)(upx * sy - upy * sx) + (double)(eps * Ez);
-      double ginv = 1.0 / sqrt(1.0 + (double)ux * ux + (double)uy * uy + uz * uz);
-      x += g.dt * ((double)ux * ginv);
-      y += g.dt * ((double)uy * ginv);
-      z += g.dt * (uz * ginv);
-      p.x[i] = x;
-      p.y[i] = y;
-      p.z[i] = z;
-      p.ux[i] = ux;
-      p.uy[i] = uy;
-      p.uz[i] = uz;
-      k = cell_key(shape_at(x, y, z, zmin, g), g);
+  PushRec r[kPushPer];
+#pragma unroll
+  for (int q = 0; q < kPushPer; ++q) {
+    const int i = base + q * 256;
+    if (i < n) {
+      r[q].x = p.x[i];
+      r[q].y = p.y[i];
+      r[q].z = p.z[i];
+      r[q].uz = p.uz[i];
+      r[q].ux = p.ux[i];
+      r[q].uy = p.uy[i];
+      r[q].sp = p.sp[i];
     }
-    key[i] = k;
   }
-  wave_count(k, count);
+  uint32_t k[kPushPer];
+#pragma unroll
+  for (int q = 0; q < kPushPer; ++q) {
+    k[q] = kInvalidKey;
+    if (base + q * 256 < n) k[q] = push_one<M>(r[q], gf, g, sc, zmin, kill);
+  }
+#pragma unroll
+  for (int q = 0; q < kPushPer; ++q) {
+    const int i = base + q * 256;
+    if (i < n) {
+      if (k[q] != (uint32_t)g.ncells) {
+        p.x[i] = r[q].x;
+        p.y[i] = r[q].y;
+        p.z[i] = r[q].z;
+        p.uz[i] = r[q].uz;
+        p.ux[i] = r[q].ux;
+        p.uy[i] = r[q].uy;
+      }
+      key[i] = k[q];
+    }
+    wave_count(k[q], count);
+  }
 }
 
 // key + histogram of the current positions (no push): background deposit at setup
@@ -441,7 +475,7 @@ static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 void launch_gather_push(const Parts& p, const float2* gf, const Grid& g, const SpeciesConst& sc,
                         const DevState* st, uint32_t* key, int* count, int cap, hipStream_t s) {
-  dim3 grid(nblk(cap, 256));
+  dim3 grid(nblk(cap, kPushPer * 256));
   switch (g.nmodes) {
     case 1: hipLaunchKernelGGL(k_gather_push<1>, grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
     case 2: hipLaunchKernelGGL(k_gather_push<2>, grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
