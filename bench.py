@@ -138,6 +138,58 @@ def cpu_baseline(wl_name, stride=8):
                        f"single-threaded NumPy, Hankel products use {blas} BLAS threads")}
 
 
+def scan_bench(args):
+    """Scan runs/hour at matched slice energy spread: every run is done twice,
+    batched (graph replays, autotuned, BF16x3 split-precision Hankel products)
+    and plain (eager steps, FP32 Hankel products, one run at a time); a run
+    counts when its final witness slice energy spread agrees within 1 %."""
+    import torch
+    from paper_1611_05712_amd import Simulation, H_BF16X3, H_FP32
+    from paper_1611_05712_amd.scan import run_batched, run_plain, slice_energy_spread
+    from workloads import scan_instances, scan_workload
+    insts = scan_instances()
+    if args.scan > 0:
+        insts = insts[:args.scan]
+    t0 = time.perf_counter()
+    fast, plain = [], []
+    for inst in insts:
+        wl = scan_workload(inst, args.scan_steps)
+        fast.append(Simulation.from_workload(wl, hankel_prec=H_BF16X3, device="cuda:0"))
+        plain.append(Simulation.from_workload(wl, hankel_prec=H_FP32, device="cuda:0"))
+        del wl
+        print(f"init {inst.index}: nz {inst.nz} nr {inst.nr} p {inst.order}", file=sys.stderr, flush=True)
+    init_s = time.perf_counter() - t0
+    plain_s = 0.0
+    for k, s in enumerate(plain):
+        plain_s += run_plain(s, args.scan_steps)
+        print(f"plain {k}: {plain_s:.2f} s", file=sys.stderr, flush=True)
+    b = run_batched(fast, args.scan_steps)
+    rows, matched = [], 0
+    for inst, f, p in zip(insts, fast, plain):
+        ef, ep = slice_energy_spread(f), slice_energy_spread(p)
+        ok = bool(abs(ef - ep) <= 0.01 * abs(ep))   # False when either is NaN
+        dw = p.diagnostics("witness", slice_len=0.02975, allow_nan=True)
+        matched += int(ok)
+        rows.append({"run": inst.index, "order": inst.order, "nz": inst.nz, "nr": inst.nr,
+                     "dz": round(inst.dz, 5), "dr": round(inst.dr, 5), "gamma_w": round(inst.gamma_w, 1),
+                     "spread_batched": ef, "spread_plain": ep, "matched": ok,
+                     "witness_live": dw["n"], "witness_slices": dw["n_slices"], "nan_flag": dw["nan_flag"]})
+    for s in fast + plain:
+        s.close()
+    torch.cuda.synchronize()
+    n = len(insts)
+    out = {"metric": "scan runs/hour at matched slice energy spread (1 %)",
+           "value": matched / b["total_s"] * 3600.0, "unit": "runs/hour", "runs": n, "matched": matched,
+           "steps": args.scan_steps, "batched_s": round(b["total_s"], 3),
+           "batched_note": (f"all {args.scan_steps} steps of every run: per-run autotuning trials, then "
+                            f"{b['batch_steps']} steps in one batch ({b['batch_s']:.3f} s); BF16x3 "
+                            "Hankel products; device-resident, initialisation excluded"),
+           "plain_s": round(plain_s, 3), "plain_runs_per_hour": n / plain_s * 3600.0,
+           "init_s": round(init_s, 1), "tunings": b["tunings"], "runs_detail": rows,
+           "data": "synthetic", "n_gpus": 1}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +198,13 @@ def main():
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--hankel-prec", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager steps instead of replays of the captured two-step HIP graph")
+    ap.add_argument("--scan", type=int, default=0, metavar="N",
+                    help="instead of the c1 bench: the parameter scan (first N runs of the "
+                         "64-run scan, 0 = off; -1 = all), batched with split-precision Hankel "
+                         "products against plain FP32 runs; prints its own JSON line")
+    ap.add_argument("--scan-steps", type=int, default=500)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 5 device-to-device copies of BYTES (scale of the rocprofv3 "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -167,6 +226,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 4 * n, "launches": 5}))
         return
+    if args.scan:
+        scan_bench(args)
+        return
     from paper_1611_05712_amd import Simulation
     from workloads import preset
 
@@ -174,7 +236,7 @@ def main():
     wl = preset(args.workload)
     sim = Simulation.from_workload(wl, hankel_prec=prec, device="cuda:0")
     t0 = time.perf_counter()
-    sim.step(args.warmup)
+    (sim.step if args.eager else sim.step_graph)(args.warmup)
     sim.sync()
     warm_s = time.perf_counter() - t0
     n_before = sim.num_particles()
@@ -182,7 +244,10 @@ def main():
     # timed region: K whole cycles, no instrumentation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps)
+    if args.eager:
+        sim.step(args.steps)
+    else:
+        sim.step_graph(args.steps)
     sim.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -233,7 +298,8 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "mobile_particles": int(n_part), "cells_per_mode": wl.nz * wl.nr,
                    "modes": wl.n_modes, "order": wl.order,
-                   "hankel_prec": args.hankel_prec, "positions": "f64"},
+                   "hankel_prec": args.hankel_prec, "positions": "f64",
+                   "stepping": "eager" if args.eager else "hip graph, two steps per replay"},
         "field_cell_updates_per_s": cells * args.steps / (spectral_ms / 1e3) if spectral_ms else None,
         "roofline": roofline,
         "kernels": kernels,

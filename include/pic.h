@@ -57,11 +57,20 @@ typedef enum {
   PIC_ENUMERIC = -5   /* NaN or Inf found by pic_diagnostics */
 } pic_status;
 
-/* Radial wavenumber grid of the discrete Hankel transform. */
+/* Radial wavenumber grid of the discrete Hankel transform.  In mode m the
+   components F_-, F_z and F_+ are synthesised with Bessel functions of order
+   m - 1, m and m + 1 at the same wavenumbers; the forward transform is the
+   pseudo-inverse of that synthesis matrix (singular values below 1e-4 of
+   the largest dropped). */
 typedef enum {
-  PIC_KPERP_J0_ZEROS = 0, /* k_i = j_{0,i} / R for every mode (default) */
-  PIC_KPERP_SINE = 1,     /* k_i = (i + 1) pi / R */
-  PIC_KPERP_JM_ZEROS = 2  /* k_i = j_{m,i} / R for mode m */
+  PIC_KPERP_J0_ZEROS = 0, /* k_i = j_{0,i} / R for every mode.  Well conditioned, but in
+                             mode 1 the order-2 basis is neither orthogonal nor of equal
+                             norm, and mode 1 grows without bound in beam-plasma runs */
+  PIC_KPERP_SINE = 1,     /* k_i = (i + 1) pi / R (comparison only) */
+  PIC_KPERP_JM_ZEROS = 2  /* k_i = j_{m,i} / R for mode m (recommended): the three
+                             orders share one norm and are orthogonal, so the field
+                             energy the spectral update conserves is the one the
+                             particles see */
 } pic_kperp_grid;
 
 /* Arithmetic of the Hankel-transform matrix products. */
@@ -241,6 +250,45 @@ typedef enum {
 int pic_timing_enable(pic_ctx* ctx, int enable);
 /* Errors: PIC_EINVAL (bad timer), PIC_EHIP. */
 int pic_timing_read(pic_ctx* ctx, int timer, double* total_ms, int64_t* launches);
+
+/* --------------------------------------------------------------------------
+ * Repeated steps without host launch overhead, batches of independent runs,
+ * and performance tunables (used by parameter scans: many instances of the
+ * cycle with different grids, orders and beams run side by side).
+ * ------------------------------------------------------------------------ */
+
+/* Launch parameters that change speed only (results agree to rounding). */
+typedef struct {
+  int32_t gemm_tile_m;     /* output rows per Hankel-product workgroup tile: 32 or 64
+                              (must divide nr) */
+  int32_t deposit_chunk;   /* particles per deposit work item of a dense tile: 2048, 4096
+                              or 8192 (tiles above 3x this are cut into such chunks) */
+} pic_tuning;
+
+/* Read / set the tunables.  Errors: PIC_EINVAL (null or unsupported values). */
+int pic_get_tuning(pic_ctx* ctx, pic_tuning* t);
+int pic_set_tuning(pic_ctx* ctx, const pic_tuning* t);
+
+/* n whole steps, enqueued as replays of a HIP graph that holds two steps of
+ * this context (captured at the first call and again whenever a tunable or
+ * the pending window shift changed; a first step after pic_init or
+ * pic_set_field runs eagerly).  The context's stream must not be the legacy
+ * null stream, timing must be off and the call must start a step (PIC_ESTATE
+ * otherwise).  Asynchronous like pic_step; same results to rounding. */
+int pic_step_graph(pic_ctx* ctx, int n);
+
+/* n steps of each of n_ctx independent contexts (distinct streams), issued two
+ * steps at a time in round-robin so that the instances overlap on the GPU;
+ * each context advances as with pic_step_graph.  Errors as pic_step_graph for
+ * the first failing context; contexts before it have advanced. */
+int pic_batch_step(pic_ctx* const* ctxs, int n_ctx, int n);
+
+/* Autotuner: for every supported (gemm_tile_m, deposit_chunk) pair, runs two
+ * untimed and then steps_per_trial timed graph steps (HIP events on the
+ * context's stream), keeps the fastest pair and returns it with its time per
+ * step in ms.  The simulation advances by all these steps.  Synchronizes.
+ * Errors: PIC_EINVAL (steps_per_trial < 2, null stream, timing on). */
+int pic_autotune(pic_ctx* ctx, int steps_per_trial, pic_tuning* best, double* best_ms);
 
 /* --------------------------------------------------------------------------
  * Kernel-level entry points used by parity tests and benchmarks.  Each runs

@@ -1,19 +1,25 @@
 """The oracle's PIC cycle (FP64, plain NumPy).
 
-Per step n (fields E^n, B^n live at integer times in real space, momenta at
-half-integer times):
+The state is spectral: per mode, Eh and Bh hold E^n and B^n on the
+(k_perp, k_z) grid (momenta live at half-integer times).  E and B hold the
+real-space fields the particles see.  Per step n:
   1. gather E^n, B^n at x^n, Boris push u^{n-1/2} -> u^{n+1/2},
      move x^{n+1} = x^n + dt v^{n+1/2};
   2. deposit rho^n at x^n, J^{n+1/2} at x^{n+1/2} = (x^n + x^{n+1})/2 with
      v^{n+1/2}, rho^{n+1} at x^{n+1} (the time levels the paper's Eq. (1a)
      uses), immobile species included in both densities;
-  3. forward transforms (FFT along z, discrete Hankel along r) of E, B, J,
-     rho^n, rho^{n+1};
-  4. spectral current correction, then the order-p PSATD update;
-  5. inverse transforms to real space;
-  6. moving window (when enabled): zmin advances by dz, fields shift one cell
-     toward the tail (the head column is zeroed), particles behind the new
-     zmin are removed and a fresh lattice column is injected at the head.
+  3. forward transforms (FFT along z, discrete Hankel along r) of J, rho^n,
+     rho^{n+1};
+  4. spectral current correction, then the order-p PSATD update of Eh, Bh;
+  5. inverse transforms of Eh, Bh to real space E, B;
+  6. moving window (when enabled): zmin advances by dz; the real-space fields
+     shift one cell toward the tail and the head column is zeroed; the
+     spectral state gets the same shift, Fh <- exp(i k_z dz) (Fh - Hankel
+     transform of the departed tail column); particles behind the new zmin
+     are removed and a fresh lattice column is injected at the head.
+
+Fields written in real space with set_fields() become the state at the next
+spectral push (they are forward transformed then).
 """
 from __future__ import annotations
 
@@ -57,9 +63,13 @@ class OracleSim:
         self.n_shift = 0
         self.hankel = [sp.HankelPair(m, wl.nr, wl.dr, wl.kperp_grid) for m in range(self.M)]
         self.kzm = sp.kz_modified(sp.kz_grid(wl.nz, wl.dz), wl.dz, wl.order)[None, :]
+        self.kz = sp.kz_grid(wl.nz, wl.dz)
         shape = (self.M, 3, self.nr, self.nz)
+        self.Eh = np.zeros(shape, dtype=np.complex128)
+        self.Bh = np.zeros(shape, dtype=np.complex128)
         self.E = np.zeros(shape, dtype=np.complex128)
         self.B = np.zeros(shape, dtype=np.complex128)
+        self._real_pending = False
         self.species: List[OSpecies] = []
         for s in wl.species:
             self.species.append(OSpecies(
@@ -74,6 +84,15 @@ class OracleSim:
         self.rho_new = None
 
     # -- helpers -----------------------------------------------------------
+    def set_fields(self, E=None, B=None):
+        """Write real-space fields [M, 3, nr, nz] (components +, -, z); they
+        replace the spectral state at the next spectral push."""
+        if E is not None:
+            self.E[:] = E
+        if B is not None:
+            self.B[:] = B
+        self._real_pending = True
+
     def grid(self):
         return {"nz": self.nz, "nr": self.nr, "dz": self.dz, "dr": self.dr, "zmin": self.zmin}
 
@@ -118,17 +137,22 @@ class OracleSim:
             hk = self.hankel[m]
             kp = hk.k[:, None]
             nus = sp.hankel_orders(m)
-            Eh = tuple(hk.forward(self.E[m, c], nus[c]) for c in range(3))
-            Bh = tuple(hk.forward(self.B[m, c], nus[c]) for c in range(3))
+            if self._real_pending:
+                for c in range(3):
+                    self.Eh[m, c] = hk.forward(self.E[m, c], nus[c])
+                    self.Bh[m, c] = hk.forward(self.B[m, c], nus[c])
             Jh = tuple(hk.forward(self.J[m, c], nus[c]) for c in range(3))
             r0 = hk.forward(self.rho_old[m], m)
             r1 = hk.forward(self.rho_new[m], m)
             if self.correct:
                 Jh = sp.current_correction(Jh, r0, r1, self.dt, kp, self.kzm)
-            En, Bn = sp.psatd_push(Eh, Bh, Jh, r0, r1, self.dt, kp, self.kzm)
+            En, Bn = sp.psatd_push(tuple(self.Eh[m]), tuple(self.Bh[m]), Jh, r0, r1, self.dt, kp, self.kzm)
             for c in range(3):
+                self.Eh[m, c] = En[c]
+                self.Bh[m, c] = Bn[c]
                 self.E[m, c] = hk.backward(En[c], nus[c])
                 self.B[m, c] = hk.backward(Bn[c], nus[c])
+        self._real_pending = False
         if self.moving_window:
             self.move_window()
 
@@ -136,6 +160,19 @@ class OracleSim:
     def move_window(self):
         self.n_shift += 1
         self.zmin = self.zmin0 + self.n_shift * self.dz
+        if not self._real_pending:
+            # a one-cell periodic shift toward the tail multiplies the z
+            # spectrum by exp(i k_z dz); removing the departed column first
+            # (a delta in z: the same radial transform at every k_z) leaves
+            # the head empty
+            ramp = np.exp(1j * self.kz * self.dz)[None, :]
+            for m in range(self.M):
+                hk = self.hankel[m]
+                nus = sp.hankel_orders(m)
+                for Fh, F in ((self.Eh, self.E), (self.Bh, self.B)):
+                    for c in range(3):
+                        tail = hk.F[nus[c]] @ F[m, c, :, 0]
+                        Fh[m, c] = ramp * (Fh[m, c] - tail[:, None])
         for F in (self.E, self.B):
             F[..., :-1] = F[..., 1:].copy()
             F[..., -1] = 0.0

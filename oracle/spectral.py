@@ -71,17 +71,21 @@ def r_grid(nr: int, dr: float) -> np.ndarray:
     return (np.arange(nr, dtype=np.float64) + 0.5) * dr
 
 
-def kperp_grid(m: int, nr: int, dr: float, kind: int = KPERP_J0_ZEROS) -> np.ndarray:
+def kperp_grid(m: int, nr: int, dr: float, kind: int = KPERP_JM_ZEROS) -> np.ndarray:
     """Radial wavenumbers of mode m (all strictly positive).
 
-    KPERP_J0_ZEROS (default): k_i = j_{0,i}/R for every mode.  On this grid
-      the synthesis bases of orders 0, 1 and 2 all interpolate smooth data
-      accurately, so the spectral operators reproduce real-space derivatives,
-      and the matrices stay well conditioned (< 2e4 at Nr = 256).
-    KPERP_SINE: k_i = (i + 1) pi / R (well conditioned but a poor interpolant
-      for orders 0 and 1; kept for comparison).
-    KPERP_JM_ZEROS: k_i = j_{m,i}/R (the order-0 basis of mode 1 is then
-      nearly singular)."""
+    KPERP_JM_ZEROS (default): k_i = j_{m,i}/R.  At the zeros of J_m the three
+      bases J_{m-1}(k r), J_m(k r), J_{m+1}(k r) of the (-, z, +) components all
+      satisfy Dini boundary conditions at R and have the same norm
+      (R^2/2) J_{m+1}(k R)^2 for every k, so the energy the spectral PSATD
+      update conserves, sum_k N_k (2|E+|^2 + 2|E-|^2 + |Ez|^2), is the field
+      energy the particles exchange with.  The order-0 basis of mode 1
+      (Neumann at R) misses the constant eigenfunction, which leaves one
+      near-null direction in its synthesis matrix (see HankelPair).
+    KPERP_J0_ZEROS: k_i = j_{0,i}/R for every mode.  Well conditioned, but the
+      order-2 basis of mode 1 is neither orthogonal nor of equal norm, and
+      mode 1 then grows without bound in a beam-plasma run.
+    KPERP_SINE: k_i = (i + 1) pi / R (a poor interpolant; for comparison)."""
     R = nr * dr
     if kind == KPERP_SINE:
         return (np.arange(nr, dtype=np.float64) + 1.0) * np.pi / R
@@ -97,11 +101,22 @@ def bessel_synthesis(nu: int, r: np.ndarray, k: np.ndarray) -> np.ndarray:
     return jv(nu, np.outer(r, k))
 
 
-class HankelPair:
-    """Forward F_nu = inverse(B_nu) and backward B_nu matrices of one mode for
-    the three orders nu = m - 1, m, m + 1 used by F_-, scalars/F_z and F_+."""
+# singular values of a synthesis matrix below this fraction of its largest are
+# dropped from the forward transform
+PINV_RCOND = 1e-4
 
-    def __init__(self, m: int, nr: int, dr: float, kind: int = KPERP_J0_ZEROS):
+
+class HankelPair:
+    """Backward B_nu and forward F_nu matrices of one mode for the three orders
+    nu = m - 1, m, m + 1 used by F_-, scalars/F_z and F_+.
+
+    F_nu is the Moore-Penrose pseudo-inverse of B_nu with singular values below
+    PINV_RCOND * sigma_max dropped.  For the default grid this is the exact
+    inverse except for isolated near-null directions (mode 1, order 0: the
+    constant eigenfunction its Neumann basis lacks; higher modes: near-axis
+    orders), which are projected out instead of amplified."""
+
+    def __init__(self, m: int, nr: int, dr: float, kind: int = KPERP_JM_ZEROS):
         self.m = m
         self.r = r_grid(nr, dr)
         self.k = kperp_grid(m, nr, dr, kind)
@@ -110,7 +125,7 @@ class HankelPair:
         for nu in (m - 1, m, m + 1):
             B = bessel_synthesis(nu, self.r, self.k)
             self.B[nu] = B
-            self.F[nu] = np.linalg.inv(B)
+            self.F[nu] = np.linalg.pinv(B, rcond=PINV_RCOND)
 
     def forward(self, g: np.ndarray, nu: int) -> np.ndarray:
         """Real space [r, z] -> spectral [k_perp, k_z]: FFT along z, then F_nu."""

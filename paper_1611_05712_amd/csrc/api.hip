@@ -105,7 +105,7 @@ struct pic_ctx {
   double* setup64;
   const float** ptr_tab; // device pointer tables (see init)
   double *diag_partial, *diag_out, *diag_slices;
-  int* misc;             // [0] GJ fail, [1..2] uniform check, [3] counter
+  int* misc;             // [0] SVD unconverged, [1..2] uniform check, [3] counter
   bool have_bg;
   // host mirrors
   int phase;             // 0: expect gather_push, 1: expect deposit, 2: expect spectral_push
@@ -122,6 +122,11 @@ struct pic_ctx {
   size_t ev_used;
   // pointer-table offsets (entries of ptr_tab)
   int pt_fwd_src, pt_fwd_eb, pt_inv_eb, pt_tail;
+  // captured two-step graph and the launch parameters it was captured with
+  hipGraphExec_t graph;
+  bool graph_ok;
+  int graph_bm, graph_chunk;
+  bool graph_shift;
 };
 
 namespace {
@@ -231,7 +236,7 @@ size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
   double* kperp = cv.take<double>(M * nr);
   float2* tw = cv.take<float2>(nz);
   float* mats = cv.take<float>((size_t)M * 6 * nr * nr);
-  double* setup64 = cv.take<double>((size_t)6 * nr * nr);
+  double* setup64 = cv.take<double>((size_t)9 * nr * nr);
   const float** ptr_tab = cv.take<const float*>((size_t)(3 * (5 + 6 + 6) + 6) * M);
   double* dpart = cv.take<double>(diag_partial_doubles());
   double* dout = cv.take<double>(32);
@@ -480,17 +485,17 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
   const double R = nr * cfg->dr;
   for (int m = 0; m < M; ++m) launch_kperp(x->kperp + (size_t)m * nr, nr, R, cfg->kperp_grid, m, s);
   for (int m = 0; m < M; ++m) {
-    double* B = x->setup64;                       // 3 synthesis matrices
-    double* F = x->setup64 + (size_t)3 * nr * nr; // 3 copies inverted in place
+    double* B = x->setup64;                        // 3 synthesis matrices
+    double* W = x->setup64 + (size_t)3 * nr * nr;  // their Jacobi factors
+    double* V = x->setup64 + (size_t)6 * nr * nr;
     for (int slot = 0; slot < 3; ++slot) {
       int nu = m - 1 + slot;
       launch_bessel_matrix(B + (size_t)slot * nr * nr, x->kperp + (size_t)m * nr, nr, cfg->dr, nu, s);
     }
-    PIC_CK(hipMemcpyAsync(F, B, (size_t)3 * nr * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
-    launch_gauss_jordan(F, 3, nr, x->misc + 0, s);
+    launch_jacobi_svd(B, W, V, 3, nr, x->misc + 0, s);
     for (int slot = 0; slot < 3; ++slot) {
       int nu = m - 1 + slot;
-      launch_to_f32_transposed(F + (size_t)slot * nr * nr, mat(x, m, nu, 0), nr, s);
+      launch_pinv_f32(W + (size_t)slot * nr * nr, V + (size_t)slot * nr * nr, mat(x, m, nu, 0), nr, kPinvRcond, s);
       launch_to_f32_transposed(B + (size_t)slot * nr * nr, mat(x, m, nu, 1), nr, s);
     }
   }
@@ -587,7 +592,7 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
   if (rc == PIC_OK) {
     int misc[3];
     PIC_CK(hipMemcpy(misc, x->misc, sizeof(misc), hipMemcpyDeviceToHost));
-    if (misc[0]) rc = PIC_EINVAL;   // singular Hankel matrix
+    if (misc[0]) rc = PIC_EINVAL;   // Jacobi SVD of a Hankel matrix did not converge
     if (x->have_bg && cfg->moving_window) {
       float dmax, amax;
       memcpy(&dmax, &misc[1], 4);
@@ -891,7 +896,163 @@ int pic_free(pic_ctx* x) {
   if (!x) return PIC_EINVAL;
   int rc = sync(x);
   for (hipEvent_t e : x->ev_pool) (void)hipEventDestroy(e);
+  if (x->graph_ok) (void)hipGraphExecDestroy(x->graph);
   delete x;
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// tuning, graph replay, batches
+// ---------------------------------------------------------------------------
+int pic_get_tuning(pic_ctx* x, pic_tuning* t) {
+  if (!x || !t) return PIC_EINVAL;
+  t->gemm_tile_m = 32 * gemm_tile_bm(x->nr, x->gemm_bm);
+  t->deposit_chunk = x->dep.chunk;
+  return PIC_OK;
+}
+
+int pic_set_tuning(pic_ctx* x, const pic_tuning* t) {
+  if (!x || !t) return PIC_EINVAL;
+  if (t->gemm_tile_m != 32 && t->gemm_tile_m != 64) return PIC_EINVAL;
+  if (t->deposit_chunk != 2048 && t->deposit_chunk != 4096 && t->deposit_chunk != 8192) return PIC_EINVAL;
+  if ((x->nr % t->gemm_tile_m) != 0) return PIC_EINVAL;
+  x->gemm_bm = t->gemm_tile_m / 32;
+  x->dep.chunk = t->deposit_chunk;
+  x->dep.tile_max = 3 * t->deposit_chunk;
+  return PIC_OK;
+}
+
+namespace {
+
+// Captures two steps (the particle buffers ping-pong, so two steps return to
+// the same launch arguments) into a graph.  The host mirrors advanced by the
+// capture are restored: nothing ran.
+int capture_graph(pic_ctx* x) {
+  if (x->graph_ok) {
+    (void)hipGraphExecDestroy(x->graph);
+    x->graph_ok = false;
+  }
+  const int cur = x->cur, phase = x->phase;
+  const int64_t steps = x->steps, n_shift = x->n_shift;
+  const bool spec_pending = x->spec_pending, eb_stale = x->eb_stale;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PIC_EHIP;
+  int rc = pic_step(x, 2);
+  hipError_t e = hipStreamEndCapture(x->stream, &g);
+  x->cur = cur;
+  x->phase = phase;
+  x->steps = steps;
+  x->n_shift = n_shift;
+  x->spec_pending = spec_pending;
+  x->eb_stale = eb_stale;
+  if (rc != PIC_OK || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return rc != PIC_OK ? rc : PIC_EHIP;
+  }
+  e = hipGraphInstantiate(&x->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return PIC_EHIP;
+  x->graph_ok = true;
+  x->graph_bm = x->gemm_bm;
+  x->graph_chunk = x->dep.chunk;
+  x->graph_shift = x->spec_pending;
+  return PIC_OK;
+}
+
+// Enqueues n steps as graph replays (an odd step runs eagerly).
+int graph_steps(pic_ctx* x, int n) {
+  if (x->phase != 0) return PIC_ESTATE;
+  if (!x->stream || x->timing) return PIC_EINVAL;   // the legacy stream cannot be captured
+  for (int m = 0; m < x->M; ++m)
+    if (x->src_set[m]) return PIC_ESTATE;
+  int rc = PIC_OK;
+  // one eager step settles the one-time work (re-transform of set fields,
+  // first window shift, kernel attributes)
+  if (n > 0 && (x->steps == 0 || x->eb_stale)) {
+    rc = pic_step(x, 1);
+    if (rc) return rc;
+    --n;
+  }
+  if (n >= 2 && !(x->graph_ok && x->graph_bm == x->gemm_bm && x->graph_chunk == x->dep.chunk &&
+                  x->graph_shift == x->spec_pending)) {
+    rc = capture_graph(x);
+    if (rc) return rc;
+  }
+  for (; n >= 2; n -= 2) {
+    if (hipGraphLaunch(x->graph, x->stream) != hipSuccess) return PIC_EHIP;
+    x->steps += 2;
+    if (x->cfg.moving_window) x->n_shift += 2;
+  }
+  if (n == 1) rc = pic_step(x, 1);
+  return rc;
+}
+
+}  // namespace
+
+int pic_step_graph(pic_ctx* x, int n) {
+  if (!x || n < 0) return PIC_EINVAL;
+  return graph_steps(x, n);
+}
+
+int pic_batch_step(pic_ctx* const* ctxs, int n_ctx, int n) {
+  if (!ctxs || n_ctx < 0 || n < 0) return PIC_EINVAL;
+  for (int c = 0; c < n_ctx; ++c)
+    if (!ctxs[c]) return PIC_EINVAL;
+  // round-robin two steps at a time over the contexts' own streams, so
+  // independent instances overlap on the GPU
+  for (int done = 0; done < n; done += 2) {
+    const int k = (n - done) >= 2 ? 2 : 1;
+    for (int c = 0; c < n_ctx; ++c) {
+      int rc = graph_steps(ctxs[c], k);
+      if (rc) return rc;
+    }
+  }
+  return PIC_OK;
+}
+
+int pic_autotune(pic_ctx* x, int steps_per_trial, pic_tuning* best, double* best_ms) {
+  if (!x || steps_per_trial < 2 || !best) return PIC_EINVAL;
+  if (!x->stream || x->timing || x->phase != 0) return PIC_EINVAL;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return PIC_EHIP;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return PIC_EHIP;
+  }
+  pic_tuning cand[6];
+  int nc = 0;
+  for (int tm : {64, 32})
+    for (int ch : {2048, 4096, 8192})
+      if (x->nr % tm == 0) cand[nc++] = pic_tuning{tm, ch};
+  int rc = PIC_OK;
+  double bms = 1e300;
+  pic_tuning bt = cand[0];
+  for (int i = 0; i < nc && rc == PIC_OK; ++i) {
+    rc = pic_set_tuning(x, &cand[i]);
+    if (rc == PIC_OK) rc = graph_steps(x, 2);   // capture with these parameters, untimed
+    if (rc != PIC_OK) break;
+    (void)hipEventRecord(a, x->stream);
+    rc = graph_steps(x, steps_per_trial);
+    (void)hipEventRecord(b, x->stream);
+    if (rc != PIC_OK) break;
+    if (hipEventSynchronize(b) != hipSuccess) {
+      rc = PIC_EHIP;
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (ms < bms) {
+      bms = ms;
+      bt = cand[i];
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc == PIC_OK) rc = pic_set_tuning(x, &bt);
+  if (rc == PIC_OK) rc = sync(x);
+  *best = bt;
+  if (best_ms) *best_ms = bms / steps_per_trial;
   return rc;
 }
 

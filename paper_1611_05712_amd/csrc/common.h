@@ -12,6 +12,10 @@ constexpr int kNumComp = 11;           // E+,E-,Ez,B+,B-,Bz,J+,J-,Jz,rho^n,rho^{
 constexpr int kCompJ = 6;              // first source component
 constexpr int kNumSrc = 5;             // J+,J-,Jz,rho^n,rho^{n+1}
 constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;
+// The forward discrete Hankel transform is the pseudo-inverse of the Bessel
+// synthesis matrix: singular values below this fraction of the largest are
+// dropped (near-null directions are projected out, not amplified).
+constexpr double kPinvRcond = 1e-4;
 
 // Device-resident mutable state: kernels read and update it so that a step
 // can be captured once and replayed without host-side argument changes.

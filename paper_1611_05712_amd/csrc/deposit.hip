@@ -9,8 +9,8 @@
 //     a workgroup accumulates a (TZ + 2H + 1) x (TR + 2H + 1) node block in
 //     LDS (FP64: on gfx950 an FP64 LDS atomic is ~20x cheaper than an FP32
 //     one) and writes it to an FP32 scratch slot;
-//   * dense tiles (beam cores and compressed plasma, more than kTileMax
-//     particles) are cut into chunks of kChunk particles, each its own
+//   * dense tiles (beam cores and compressed plasma, more than tile_max
+//     particles) are cut into chunks of `chunk` particles, each its own
 //     workgroup and slot; the device builds this work list (k_tile_plan) from
 //     the sorted offsets, and k_chunk_reduce sums a tile's chunk slots into
 //     its first one;
@@ -29,8 +29,8 @@
 
 namespace pic {
 
-constexpr int kTileMax = 12288;  // a tile with more particles than this is cut into chunks
-constexpr int kChunk = 4096;     // particles per chunk of a dense tile
+constexpr int kChunkMin = 2048;  // smallest chunk of a dense tile (sizes the work list)
+constexpr int kChunkMax = 8192;  // largest chunk (keeps a work item's run table in 16 bits)
 constexpr int kTZ = 32;
 constexpr int kRun = 8;       // consecutive particles per lane per sub-chunk
 
@@ -47,6 +47,8 @@ struct Blk {
 
 struct TileGeom {
   int ntz, ntr, ntiles;
+  int tile_max;   // a tile with more particles than this is cut into chunks
+  int chunk;      // particles per chunk of a dense tile
 };
 
 // ---------------------------------------------------------------------------
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_tile_totals(const int* __restrict__ off
     s = offset[j * g.ncol + C1] - offset[j * g.ncol + C0];
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) nchunk[t] = s > kTileMax ? (s + kChunk - 1) / kChunk : 1;
+  if (lane == 0) nchunk[t] = s > tg.tile_max ? (s + tg.chunk - 1) / tg.chunk : 1;
 }
 
 // exclusive scan of chunk counts: chunk_start[0..ntiles], chunk_start[ntiles] = work items
@@ -343,8 +345,8 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
   __syncthreads();
   const int total = rowpref[kTZ];
   const bool whole = nchunk[t] == 1;
-  const int f0 = whole ? 0 : chunk * kChunk;
-  const int f1 = whole ? total : min(total, f0 + kChunk);
+  const int f0 = whole ? 0 : chunk * tg.chunk;
+  const int f1 = whole ? total : min(total, f0 + tg.chunk);
   const double zmin = st->zmin;
   const double dt = g.dt;
   // Runs: every cell's particles (clipped to this chunk) are cut into runs of
@@ -590,7 +592,9 @@ DepositShape deposit_shape(int nz, int nr, int nmodes, int halo, int64_t cap) {
   d.ntz = nz / d.TZ;
   d.ntr = (nr + 1 + d.TR - 1) / d.TR;   // key columns 0..nr
   d.ntiles = d.ntz * d.ntr;
-  d.max_items = d.ntiles + (int)((cap + kChunk - 1) / kChunk);
+  d.max_items = d.ntiles + (int)((cap + kChunkMin - 1) / kChunkMin);
+  d.chunk = 4096;
+  d.tile_max = 3 * d.chunk;
   const int bz = d.TZ + 2 * halo + 1, br = d.TR + 2 * halo + 1;
   const int nv = 5 + 10 * (nmodes - 1);
   d.acc_floats2 = ((size_t)nv * bz * br + 1) / 2;     // FP32 scratch slot per work item
@@ -602,7 +606,7 @@ template <int TR, int H, int M>
 static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chunk_start, float2* scratch,
                        float2* real, const float2* bg, const Grid& g, const DepositShape& d, DevState* st,
                        int stages, hipStream_t s) {
-  TileGeom tg{d.ntz, d.ntr, d.ntiles};
+  TileGeom tg{d.ntz, d.ntr, d.ntiles, d.tile_max, d.chunk};
   const size_t lds = (size_t)Vals<M>::N * Blk<TR, H>::NODES * sizeof(double);
   if (stages & kDepPlan) {
     hipLaunchKernelGGL((k_tile_totals<TR>), dim3((d.ntiles + 3) / 4), dim3(256), 0, s, offset, g, tg, nchunk);

@@ -32,7 +32,8 @@ struct DiagMeans {
 void launch_kz_table(double* kz, double* kzm, int nz, double dz, int order, hipStream_t st);
 void launch_kperp(double* kperp, int nr, double R, int kind, int m, hipStream_t st);
 void launch_bessel_matrix(double* B, const double* kperp, int nr, double dr, int nu, hipStream_t st);
-void launch_gauss_jordan(double* A, int count, int n, int* fail, hipStream_t st);
+void launch_jacobi_svd(const double* A, double* W, double* V, int count, int n, int* fail, hipStream_t st);
+void launch_pinv_f32(const double* W, const double* V, float* out, int n, double rcond, hipStream_t st);
 void launch_to_f32_transposed(const double* in, float* out, int n, hipStream_t st);
 void launch_twiddles(float2* tw, int n, hipStream_t st);
 
@@ -52,6 +53,8 @@ struct DepositShape {
   int max_items;        // workgroups launched (upper bound of the work list)
   size_t acc_floats2;   // FP32 scratch slot per work item, in float2 units (values x block nodes)
   size_t lds_bytes;     // FP64 LDS block of one workgroup
+  int chunk;            // particles per chunk of a dense tile (2048 .. 8192, tunable)
+  int tile_max;         // tiles above this many particles are chunked (3 x chunk)
 };
 DepositShape deposit_shape(int nz, int nr, int nmodes, int halo, int64_t cap);
 // stages of the deposit: work-list planning, tile accumulation, node combine

@@ -26,6 +26,7 @@ EXPORTED = (
     "pic_step", "pic_sync", "pic_diagnostics", "pic_get_field", "pic_set_field",
     "pic_num_particles", "pic_get_particles", "pic_get_state", "pic_free", "pic_strerror",
     "pic_fft_z", "pic_dht_gemm", "pic_timing_enable", "pic_timing_read",
+    "pic_get_tuning", "pic_set_tuning", "pic_step_graph", "pic_batch_step", "pic_autotune",
 )
 TIMERS = ("gather_push", "sort", "deposit", "fft_fwd", "dht_fwd", "psatd", "dht_inv", "fft_inv",
           "window", "scan", "dep_plan", "dep_combine", "pack")
@@ -43,6 +44,10 @@ class pic_config(ctypes.Structure):
                 ("dt", ctypes.c_double), ("z_min", ctypes.c_double),
                 ("moving_window", ctypes.c_int32), ("kperp_grid", ctypes.c_int32),
                 ("hankel_prec", ctypes.c_int32), ("current_correction", ctypes.c_int32)]
+
+
+class pic_tuning(ctypes.Structure):
+    _fields_ = [("gemm_tile_m", ctypes.c_int32), ("deposit_chunk", ctypes.c_int32)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -104,6 +109,11 @@ def load(path: str = LIB_PATH):
     L.pic_dht_gemm.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
     L.pic_timing_enable.argtypes = [vp, i32]
     L.pic_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    L.pic_get_tuning.argtypes = [vp, ctypes.POINTER(pic_tuning)]
+    L.pic_set_tuning.argtypes = [vp, ctypes.POINTER(pic_tuning)]
+    L.pic_step_graph.argtypes = [vp, i32]
+    L.pic_batch_step.argtypes = [ctypes.POINTER(vp), i32, i32]
+    L.pic_autotune.argtypes = [vp, i32, ctypes.POINTER(pic_tuning), ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTED:
         if name != "pic_strerror":
             getattr(L, name).restype = ctypes.c_int
@@ -139,7 +149,7 @@ class Simulation:
     density, diag)."""
 
     def __init__(self, nz, nr, n_modes, order, dz, dr, dt, z_min, species: Sequence,
-                 moving_window=False, kperp_grid=KPERP_J0_ZEROS, hankel_prec=H_FP32,
+                 moving_window=False, kperp_grid=KPERP_JM_ZEROS, hankel_prec=H_FP32,
                  current_correction=True, max_particles=0, device="cuda:0", stream=None):
         import torch
         L = load()
@@ -172,7 +182,10 @@ class Simulation:
         _check(L.pic_workspace_bytes(ctypes.byref(self.cfg), arr, len(species), max_particles,
                                      ctypes.byref(nbytes)), "pic_workspace_bytes")
         self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): graph capture needs a
+        # non-null stream, and contexts of a batch overlap on separate streams
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.workspace.record_stream(self.stream)
         ctx = ctypes.c_void_p()
         _check(L.pic_init(ctypes.byref(self.cfg), arr, len(species), max_particles,
                           ctypes.c_void_p(self.workspace.data_ptr()), nbytes.value,
@@ -198,6 +211,25 @@ class Simulation:
 
     def step(self, n: int = 1):
         _check(self._L.pic_step(self._ctx, int(n)), "pic_step")
+
+    def step_graph(self, n: int = 1):
+        _check(self._L.pic_step_graph(self._ctx, int(n)), "pic_step_graph")
+
+    def tuning(self) -> dict:
+        t = pic_tuning()
+        _check(self._L.pic_get_tuning(self._ctx, ctypes.byref(t)), "pic_get_tuning")
+        return {"gemm_tile_m": t.gemm_tile_m, "deposit_chunk": t.deposit_chunk}
+
+    def set_tuning(self, gemm_tile_m: int, deposit_chunk: int):
+        t = pic_tuning(int(gemm_tile_m), int(deposit_chunk))
+        _check(self._L.pic_set_tuning(self._ctx, ctypes.byref(t)), "pic_set_tuning")
+
+    def autotune(self, steps_per_trial: int = 4):
+        t = pic_tuning()
+        ms = ctypes.c_double()
+        _check(self._L.pic_autotune(self._ctx, int(steps_per_trial), ctypes.byref(t), ctypes.byref(ms)),
+               "pic_autotune")
+        return {"gemm_tile_m": t.gemm_tile_m, "deposit_chunk": t.deposit_chunk, "ms_per_step": ms.value}
 
     def sync(self):
         _check(self._L.pic_sync(self._ctx), "pic_sync")
@@ -282,6 +314,16 @@ class Simulation:
 # ---------------------------------------------------------------------------
 # kernel-level entry points
 # ---------------------------------------------------------------------------
+def batch_step(sims: Sequence["Simulation"], n: int):
+    """n steps of every simulation, their graph replays interleaved over the
+    simulations' own streams (pic_batch_step)."""
+    if not sims:
+        return
+    L = load()
+    arr = (ctypes.c_void_p * len(sims))(*[s._ctx for s in sims])
+    _check(L.pic_batch_step(arr, len(sims), int(n)), "pic_batch_step")
+
+
 def fft_z(t, inverse: bool = False, stream=None):
     """In-place batched FFT along the last axis of a complex64 CUDA tensor."""
     import torch

@@ -5,7 +5,7 @@ import pytest
 
 from oracle.cycle import OracleSim
 from oracle.diag import beam_moments
-from workloads import (KPERP_J0_ZEROS, Species, Workload, preset, random_particles,
+from workloads import (KPERP_JM_ZEROS, Species, Workload, preset, random_particles,
                        random_spectral)
 
 pytestmark = pytest.mark.gpu
@@ -47,7 +47,7 @@ def _random_fields(wl, seed, smooth=True):
 def _vacuum(nz=128, nr=64, order=16, moving=False, dt=None):
     dz = 0.05
     return Workload("vac", nz, nr, 2, order, dz, 0.05, dz if dt is None else dt, 0.0, moving,
-                    KPERP_J0_ZEROS, 1, [])
+                    KPERP_JM_ZEROS, 1, [])
 
 
 COMPS = ["E+", "E-", "Ez", "B+", "B-", "Bz"]
@@ -64,8 +64,7 @@ def test_spectral_push_matches_oracle(order, nz, nr):
             sim.set_field(m, c, F[m, c])
     sim.spectral_push()
     o = OracleSim(wl)
-    o.E[:] = F[:, 0:3]
-    o.B[:] = F[:, 3:6]
+    o.set_fields(F[:, 0:3], F[:, 3:6])
     o.J = F[:, 6:9].copy()
     o.rho_old = F[:, 9].copy()
     o.rho_new = F[:, 10].copy()
@@ -89,8 +88,7 @@ def test_spectral_push_window_shift_two_steps():
     for m in range(2):
         for c in range(11):
             sim.set_field(m, c, F1[m, c])
-    o.E[:] = F1[:, 0:3]
-    o.B[:] = F1[:, 3:6]
+    o.set_fields(F1[:, 0:3], F1[:, 3:6])
     for F in (F1, F2):
         for m in range(2):
             for c in range(6, 11):
@@ -212,8 +210,7 @@ def test_gather_push_matches_oracle():
     for m in range(2):
         for c in range(6):
             sim.set_field(m, c, F[m, c])
-    o.E[:] = F[:, 0:3]
-    o.B[:] = F[:, 3:6]
+    o.set_fields(F[:, 0:3], F[:, 3:6])
     sim.gather_push()
     o.gather_push()
     g = sim.get_particles(0)

@@ -7,11 +7,11 @@ from oracle import spectral as sp
 from oracle import particles as pt
 from oracle.cycle import OracleSim
 from oracle.diag import beam_moments
-from workloads import Workload, Species, preset, KPERP_J0_ZEROS
+from workloads import Workload, Species, preset, KPERP_JM_ZEROS, KPERP_J0_ZEROS
 
 
-def _empty_workload(nz=32, nr=16, order=8, moving=False):
-    return Workload("vac", nz, nr, 2, order, 0.1, 0.1, 0.1, 0.0, moving, KPERP_J0_ZEROS, 1, [])
+def _empty_workload(nz=32, nr=16, order=8, moving=False, kind=KPERP_JM_ZEROS):
+    return Workload("vac", nz, nr, 2, order, 0.1, 0.1, 0.1, 0.0, moving, kind, 1, [])
 
 
 @pytest.mark.parametrize("order", [0, 8])
@@ -20,19 +20,22 @@ def test_vacuum_mode_through_real_space(order):
     # functions (E_+ ~ J_{m+1}, E_- ~ J_{m-1}) must come back after n full
     # cycles (forward transforms, PSATD, inverse transforms) scaled by
     # cos(n k dt): pins the Hankel orders, FFT normalization and dispersion
-    wl = _empty_workload(order=order)
+    # (on the zeros of J_0, where every order used is full rank, so the round
+    # trip through real space is exact)
+    wl = _empty_workload(order=order, kind=KPERP_J0_ZEROS)
     sim = OracleSim(wl)
     iz, ik = 3, 2
     kz = sp.kz_grid(wl.nz, wl.dz)[iz]
     kzm = sp.kz_modified(np.array([kz]), wl.dz, order)[0]
     zj = np.arange(wl.nz) * wl.dz
+    E0 = np.zeros_like(sim.E)
     for m in range(2):
         kp = sim.hankel[m].k[ik]
         r = sim.hankel[m].r
         phase = np.exp(1j * kz * zj)[None, :]
-        sim.E[m, 0] = jv(m + 1, kp * r)[:, None] * phase
-        sim.E[m, 1] = jv(m - 1, kp * r)[:, None] * phase
-    E0 = sim.E.copy()
+        E0[m, 0] = jv(m + 1, kp * r)[:, None] * phase
+        E0[m, 1] = jv(m - 1, kp * r)[:, None] * phase
+    sim.set_fields(E=E0)
     sim.J = np.zeros_like(sim.E)
     sim.rho_old = np.zeros((2, wl.nr, wl.nz), complex)
     sim.rho_new = sim.rho_old.copy()
@@ -47,9 +50,7 @@ def test_vacuum_mode_through_real_space(order):
 def _gauss_residual(sim, m):
     hk = sim.hankel[m]
     kp = hk.k[:, None]
-    nus = sp.hankel_orders(m)
-    Eh = tuple(hk.forward(sim.E[m, c], nus[c]) for c in range(3))
-    return sp.div(Eh, kp, sim.kzm) - hk.forward(sim.rho_new[m], m), \
+    return sp.div(tuple(sim.Eh[m]), kp, sim.kzm) - hk.forward(sim.rho_new[m], m), \
         np.cos(np.sqrt(kp ** 2 + sim.kzm ** 2) * sim.dt)
 
 
@@ -76,7 +77,8 @@ def test_raw_current_nearly_conserves_charge():
     # Gaussian weights) drifting with a uniform 3D velocity: the deposited
     # J^{n+1/2} (before correction) already satisfies spectral continuity to
     # ~1e-2, which pins the current's mode phases and Hankel orders (a wrong
-    # phase or order gives O(1) residuals)
+    # phase or order gives O(1) residuals).  The zeros of J_0 give full-rank
+    # transforms for every order, so nothing is projected out before the check
     g = {"nz": 64, "nr": 32, "dz": 0.1, "dr": 0.1, "zmin": 0.0}
     for cx, cy in ((1.8, 0.0), (0.0, -1.8), (1.3, 1.3)):
         s, h = 0.3, 0.03
@@ -107,7 +109,9 @@ def test_moving_window_bookkeeping():
     wl = preset("small")
     sim = OracleSim(wl)
     n_e0 = sim.species[0].x.size
-    sim.E[:] = np.arange(wl.nz)[None, None, None, :]
+    ramp = np.zeros_like(sim.E)
+    ramp[:] = np.arange(wl.nz)[None, None, None, :]
+    sim.set_fields(E=ramp)
     sim.move_window()
     assert sim.zmin == pytest.approx(wl.zmin + wl.dz)
     np.testing.assert_array_equal(sim.E[0, 0, 0, :-1], np.arange(1, wl.nz))
@@ -117,6 +121,35 @@ def test_moving_window_bookkeeping():
     assert e.x.size == n_e0
     assert e.z.min() >= sim.zmin
     assert e.z.max() < sim.zmin + wl.nz * wl.dz
+
+
+def test_window_shift_of_the_spectral_state():
+    # with a full-rank radial grid the spectral state after the window move
+    # must synthesise to exactly the real-space fields shifted by one cell
+    # with an empty head column: pins the sign of the phase ramp and the
+    # removal of the departed column
+    wl = _empty_workload(nz=32, nr=16, moving=True, kind=KPERP_J0_ZEROS)
+    sim = OracleSim(wl)
+    rng = np.random.default_rng(4)
+    shape = sim.E.shape
+    for F in (sim.Eh, sim.Bh):
+        F[:] = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    for m in range(2):
+        nus = sp.hankel_orders(m)
+        for c in range(3):
+            sim.E[m, c] = sim.hankel[m].backward(sim.Eh[m, c], nus[c])
+            sim.B[m, c] = sim.hankel[m].backward(sim.Bh[m, c], nus[c])
+    want_E = np.concatenate([sim.E[..., 1:], np.zeros(shape[:-1] + (1,))], axis=-1)
+    want_B = np.concatenate([sim.B[..., 1:], np.zeros(shape[:-1] + (1,))], axis=-1)
+    sim.move_window()
+    for m in range(2):
+        nus = sp.hankel_orders(m)
+        for c in range(3):
+            got_E = sim.hankel[m].backward(sim.Eh[m, c], nus[c])
+            got_B = sim.hankel[m].backward(sim.Bh[m, c], nus[c])
+            np.testing.assert_allclose(got_E, want_E[m, c], atol=1e-10)
+            np.testing.assert_allclose(got_B, want_B[m, c], atol=1e-10)
+    np.testing.assert_array_equal(sim.E, want_E)
 
 
 def test_diagnostics_closed_forms():
@@ -154,3 +187,4 @@ def test_c0_oracle_runs_and_stays_finite():
     s = sim.species_by_name("drive")
     out = beam_moments(s.x, s.y, s.z, s.ux, s.uy, s.uz, s.w, slice_len=0.02975)
     assert out["nan_flag"] == 0 and out["n_slices"] > 0
+

@@ -91,14 +91,50 @@ def test_kz_modified_nyquist_zero_and_convergence():
 
 # --- discrete Hankel transform pair ---------------------------------------
 @pytest.mark.parametrize("nr", [16, 64, 256])
-@pytest.mark.parametrize("kind", [sp.KPERP_J0_ZEROS, sp.KPERP_SINE])
+@pytest.mark.parametrize("kind", [sp.KPERP_JM_ZEROS, sp.KPERP_J0_ZEROS, sp.KPERP_SINE])
 def test_dht_round_trip(nr, kind):
+    # full-rank orders: F is the inverse, so the round trip is exact; orders
+    # with a dropped near-null direction (mode 1, order 0 on the zeros of J_1;
+    # mode 1, order 2 on the zeros of J_0 at large nr): B F is the orthogonal
+    # projector that removes exactly that one, isolated, direction
     for m in (0, 1):
         hk = sp.HankelPair(m, nr, 0.05, kind)
         g = random_spectral((nr, 8), seed=nr + m)
         for nu in (m - 1, m, m + 1):
-            back = hk.backward(hk.forward(g, nu), nu)
-            assert np.abs(back - g).max() < 1e-12 * np.abs(g).max() * max(1, nr / 64)
+            B, F = hk.B[nu], hk.F[nu]
+            sv = np.linalg.svd(B, compute_uv=False)
+            dropped = int((sv < sp.PINV_RCOND * sv[0]).sum())
+            P = B @ F
+            if dropped == 0:
+                back = hk.backward(hk.forward(g, nu), nu)
+                assert np.abs(back - g).max() < 1e-12 * np.abs(g).max() * max(1, nr / 64)
+            else:
+                assert (kind, m, nu) in ((sp.KPERP_JM_ZEROS, 1, 0), (sp.KPERP_J0_ZEROS, 1, 2))
+                assert dropped == 1 and sv[-2] > 100 * sp.PINV_RCOND * sv[0]
+                assert np.abs(P - P.T).max() < 1e-10 and np.abs(P @ P - P).max() < 1e-10
+                assert np.trace(P) == pytest.approx(nr - 1, abs=1e-8)
+                assert np.abs(F @ B @ F - F).max() < 1e-10 * np.abs(F).max()
+
+
+def test_jm_zero_bases_share_their_norm_and_are_orthogonal():
+    # At the zeros k of J_m, J_{m-1}(k r), J_m(k r) and J_{m+1}(k r) satisfy
+    # Dini conditions at R: int_0^R J_nu(k_i r) J_nu(k_j r) r dr = delta_ij N_i
+    # with the same N_i = R^2/2 J_{m+1}(k_i R)^2 for the three orders (this is
+    # what makes the conserved spectral energy the real-space field energy).
+    # With the zeros of J_0, the order-2 basis of mode 1 is not orthogonal.
+    from scipy.integrate import quad
+    R = 1.0
+    for m in (0, 1, 2):
+        k = jn_zeros(m, 4) / R
+        N = 0.5 * R * R * jv(m + 1, k * R) ** 2
+        for nu in (m - 1, m, m + 1):
+            for i in range(3):
+                for j in range(3):
+                    v = quad(lambda r: jv(nu, k[i] * r) * jv(nu, k[j] * r) * r, 0, R, limit=200)[0]
+                    assert v == pytest.approx(N[i] if i == j else 0.0, abs=1e-10), (m, nu, i, j)
+    k0 = jn_zeros(0, 4) / R
+    off = quad(lambda r: jv(2, k0[0] * r) * jv(2, k0[1] * r) * r, 0, R)[0]
+    assert abs(off) > 1e-3
 
 
 def test_dht_gaussian_closed_form():
@@ -127,15 +163,21 @@ def test_dht_gaussian_closed_form():
 
 
 def test_dht_conditioning_of_chosen_grids():
-    # the m = 1 grid of zeros of J_1 makes the order-0 synthesis matrix
-    # ill-conditioned; the zeros of J_0 keep every order used (-1..2) usable
+    # zeros of J_m, modes 0 and 1, Nr = 256: the order-0 synthesis of mode 1 has
+    # exactly one singular value below the cutoff (cond 2e7); every other order
+    # is well conditioned, and the truncated pseudo-inverse is bounded
     r = sp.r_grid(256, 0.05)
-    bad = np.linalg.cond(sp.bessel_synthesis(0, r, sp.kperp_grid(1, 256, 0.05, sp.KPERP_JM_ZEROS)))
-    assert bad > 1e6
     for m in (0, 1):
-        k = sp.kperp_grid(m, 256, 0.05, sp.KPERP_J0_ZEROS)
+        k = sp.kperp_grid(m, 256, 0.05, sp.KPERP_JM_ZEROS)
         for nu in (m - 1, m, m + 1):
-            assert np.linalg.cond(sp.bessel_synthesis(nu, r, k)) < 2e4
+            B = sp.bessel_synthesis(nu, r, k)
+            sv = np.linalg.svd(B, compute_uv=False)
+            if (m, nu) == (1, 0):
+                assert sv[-1] / sv[0] < 1e-6 and sv[-2] / sv[0] > 1e-2
+            else:
+                assert sv[-1] / sv[0] > 1e-3
+            F = np.linalg.pinv(B, rcond=sp.PINV_RCOND)
+            assert np.linalg.norm(F, 2) * sv[0] < 1e3
 
 
 @pytest.mark.parametrize("nr", [64, 256])
@@ -144,10 +186,11 @@ def test_spectral_gradient_reproduces_real_space_derivative(nr):
     # the gradient table (-k/2, +k/2) and synthesized with orders 2 and 0; the
     # result must equal the analytic (grad S)_+- = (dS/dr -+ S/r)/2 at the nodes.
     # This is what makes the discrete transforms a valid representation of the
-    # spectral operators; the J_0-zeros grid passes, the (i+1) pi/R grid does not.
+    # spectral operators; the zeros of J_m and of J_0 pass, the (i+1) pi/R grid
+    # does not.
     dr = 0.05
     R = nr * dr
-    for kind, tol in ((sp.KPERP_J0_ZEROS, 1e-10), (sp.KPERP_SINE, None)):
+    for kind, tol in ((sp.KPERP_JM_ZEROS, 1e-10), (sp.KPERP_J0_ZEROS, 1e-10), (sp.KPERP_SINE, None)):
         hk = sp.HankelPair(1, nr, dr, kind)
         r = hk.r
         c, s = 0.5 * R, 0.05 * R

@@ -29,7 +29,7 @@ C_LIGHT = 299792458.0
 # kperp grid choices (mirrors the enum of the C interface)
 KPERP_J0_ZEROS = 0   # every mode: zeros of J_0 / R
 KPERP_SINE = 1       # every mode: (i + 1) * pi / R
-KPERP_JM_ZEROS = 2   # mode m: zeros of J_m / R (ill-conditioned for m = 1)
+KPERP_JM_ZEROS = 2   # mode m: zeros of J_m / R (default of every preset)
 
 
 def plasma_scales(n0_m3: float) -> Tuple[float, float]:
@@ -181,7 +181,7 @@ def preset(name: str, seed: int = 0) -> Workload:
         ele, ion = _plasma_species(nz, nr, dz, dr, zmin)
         drive = _bunch_species("drive", 10_000, 100e-12, 1000.0, 0.5, 0.5,
                                zmin + 0.7 * nz * dz, seed, True)
-        return Workload("c0", nz, nr, 2, 16, dz, dr, dz, zmin, True, KPERP_J0_ZEROS, 50,
+        return Workload("c0", nz, nr, 2, 16, dz, dr, dz, zmin, True, KPERP_JM_ZEROS, 50,
                         [ele, ion, drive])
     if name == "c1":
         nz, nr, dz, dr = 2048, 256, 0.02, 0.05
@@ -191,22 +191,95 @@ def preset(name: str, seed: int = 0) -> Workload:
         drive = _bunch_species("drive", 1_000_000, 1e-9, 2000.0, 0.5, 0.5, zd, seed, False)
         wit = _bunch_species("witness", 200_000, 50e-12, 2000.0, 0.1, 0.1, zd - 4.0,
                              seed + 1, True)
-        return Workload("c1", nz, nr, 2, 32, dz, dr, dz, zmin, True, KPERP_J0_ZEROS, 2000,
+        return Workload("c1", nz, nr, 2, 32, dz, dr, dz, zmin, True, KPERP_JM_ZEROS, 2000,
                         [ele, ion, drive, wit])
     if name == "tiny":
         nz, nr, dz, dr = 64, 32, 0.1, 0.1
         zmin = 0.0
         b = _bunch_species("bunch", 64, 20e-12, 50.0, 0.3, 0.4, 3.2, seed, True)
-        return Workload("tiny", nz, nr, 2, 8, dz, dr, dz, zmin, False, KPERP_J0_ZEROS, 4, [b])
+        return Workload("tiny", nz, nr, 2, 8, dz, dr, dz, zmin, False, KPERP_JM_ZEROS, 4, [b])
     if name == "small":
         nz, nr, dz, dr = 128, 32, 0.05, 0.05
         zmin = 0.0
         ele, ion = _plasma_species(nz, nr, dz, dr, zmin)
         drive = _bunch_species("drive", 3001, 50e-12, 500.0, 0.3, 0.4,
                                zmin + 0.6 * nz * dz, seed, True)
-        return Workload("small", nz, nr, 2, 16, dz, dr, dz, zmin, True, KPERP_J0_ZEROS, 10,
+        return Workload("small", nz, nr, 2, 16, dz, dr, dz, zmin, True, KPERP_JM_ZEROS, 10,
                         [ele, ion, drive])
     raise KeyError(name)
+
+
+# ---------------------------------------------------------------------------
+# parameter scans
+# ---------------------------------------------------------------------------
+SCAN_ORDERS = (8, 16, 24, 32, 48, 64, 0)          # 0 = infinite order
+SCAN_NZ = (512, 1024, 2048)
+SCAN_NR = (128, 256)
+
+
+@dataclasses.dataclass
+class ScanInstance:
+    """One run of a parameter scan: grid, stencil order and witness beam."""
+    index: int
+    tuple_index: int
+    order: int
+    nz: int
+    nr: int
+    dz: float
+    dr: float
+    gamma_w: float
+    charge_w_C: float
+    seed: int
+
+    def features(self) -> Tuple[float, float, float, float, float]:
+        """(2/p, k_p dz, k_p dr, log gamma, witness charge in pC); 2/p = 0 for p = inf."""
+        return (0.0 if self.order == 0 else 2.0 / self.order, self.dz, self.dr,
+                math.log(self.gamma_w), self.charge_w_C * 1e12)
+
+
+def scan_instances(n_tuples: int = 9, orders=SCAN_ORDERS, seed: int = 0, extra: int = 1,
+                   nz_choices=SCAN_NZ, nr_choices=SCAN_NR) -> List[ScanInstance]:
+    """Seeded scan: n_tuples physical set-ups (N_z, N_r, k_p dz in [0.01, 0.05],
+    k_p dr in [0.03, 0.08], witness gamma in [500, 4000], witness charge in
+    [10, 100] pC; boxes shorter than 8/k_p are redrawn, since driver, 4/k_p gap
+    and witness must fit), each run at every order, plus `extra` repeats of
+    the first tuples at infinite order (64 runs for the defaults)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tuples = []
+    while len(tuples) < n_tuples:
+        nz = int(rng.choice(nz_choices))
+        nr = int(rng.choice(nr_choices))
+        dz = float(rng.uniform(0.01, 0.05))
+        dr = float(rng.uniform(0.03, 0.08))
+        g = float(math.exp(rng.uniform(math.log(500.0), math.log(4000.0))))
+        q = float(rng.uniform(10e-12, 100e-12))
+        if nz * dz < 8.0:
+            continue
+        tuples.append((nz, nr, dz, dr, g, q))
+    out = []
+    for t, (nz, nr, dz, dr, g, q) in enumerate(tuples):
+        for p in orders:
+            out.append(ScanInstance(len(out), t, p, nz, nr, dz, dr, g, q, seed * 1000 + t))
+    for e in range(extra):
+        nz, nr, dz, dr, g, q = tuples[e % len(tuples)]
+        out.append(ScanInstance(len(out), e % len(tuples), 0, nz, nr, dz, dr, g, q,
+                                seed * 1000 + e % len(tuples)))
+    return out
+
+
+def scan_workload(inst: ScanInstance, steps: int = 500) -> Workload:
+    """The beam-plasma set-up of one scan run: 2x2x4 plasma over the box with
+    immobile ions, the 1 nC drive (1e6 particles, gamma 2000, sigma 0.5) at 0.7 of
+    the box and the witness (2e5 particles, sigma 0.1) 4/k_p behind it, moving
+    window, dt = dz, two modes."""
+    zmin = 0.0
+    ele, ion = _plasma_species(inst.nz, inst.nr, inst.dz, inst.dr, zmin)
+    zd = zmin + 0.7 * inst.nz * inst.dz
+    drive = _bunch_species("drive", 1_000_000, 1e-9, 2000.0, 0.5, 0.5, zd, inst.seed, False)
+    wit = _bunch_species("witness", 200_000, inst.charge_w_C, inst.gamma_w, 0.1, 0.1, zd - 4.0,
+                         inst.seed + 1, True)
+    return Workload(f"scan{inst.index}", inst.nz, inst.nr, 2, inst.order, inst.dz, inst.dr, inst.dz,
+                    zmin, True, KPERP_JM_ZEROS, steps, [ele, ion, drive, wit])
 
 
 def random_spectral(shape, seed: int) -> np.ndarray:
