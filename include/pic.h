@@ -188,6 +188,16 @@ typedef struct {
  * nan_flag = 1) if a position or momentum of the species is not finite. */
 int pic_diagnostics(pic_ctx* ctx, const pic_diag_req* req, pic_diag_out* out);
 
+/* pic_diagnostics plus the per-slice values behind Err_sigma_gamma, Eq. (11):
+ * slice k (0 <= k < n_total) covers xi = z - <z> in [(k - n_total/2) L,
+ * (k - n_total/2 + 1) L), L = slice_len, n_total = 2 ceil(n_sigma sigma_z / L);
+ * sigma_gamma[k] is its weighted rms gamma (0 when the slice has fewer than
+ * min_per_slice macro-particles) and count[k] its macro-particle count.  The
+ * first min(cap, n_total) slices are written to the host arrays; *n_total is
+ * always set (0 when sigma_z = 0).  Synchronizes.  Errors as pic_diagnostics. */
+int pic_diagnostics_slices(pic_ctx* ctx, const pic_diag_req* req, pic_diag_out* out, double* sigma_gamma,
+                           double* count, int32_t cap, int32_t* n_total);
+
 /* Copies one field component of one mode to host memory ([nr][nz] complex
  * float32, 8*nr*nz bytes).  spectral = 0: real space; 1: spectral.  E, B are
  * the current fields; J, rho are those of the last deposit (spectral J is after

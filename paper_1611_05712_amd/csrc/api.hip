@@ -819,7 +819,11 @@ int pic_get_state(pic_ctx* x, double* z_min, int64_t* steps) {
   return PIC_OK;
 }
 
-int pic_diagnostics(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out) {
+namespace {
+// Moments of one species (two passes) and, when `slice_sigma` is given, the
+// weighted rms gamma of every slice (0 for a skipped slice).
+int diag_run(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out, std::vector<double>* slice_sigma,
+             std::vector<double>* slice_count) {
   if (!x || !req || !out) return PIC_EINVAL;
   if (req->species < 0 || req->species >= x->n_species || !x->sp[req->species].mobile) return PIC_EINVAL;
   if (!(req->slice_len > 0) || !(req->n_sigma > 0)) return PIC_EINVAL;
@@ -881,15 +885,39 @@ int pic_diagnostics(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out) {
     if (rc) return rc;
     double sum = 0;
     int kept = 0;
+    if (slice_sigma) slice_sigma->assign(ns, 0.0);
+    if (slice_count) slice_count->assign(ns, 0.0);
     for (int k = 0; k < ns; ++k) {
+      if (slice_count) (*slice_count)[k] = ha[3 * k];
       if (ha[3 * k] < req->min_per_slice || !(ha[3 * k + 1] > 0)) continue;
-      sum += sqrt(hv[k] / ha[3 * k + 1]);
+      const double sg = sqrt(hv[k] / ha[3 * k + 1]);
+      if (slice_sigma) (*slice_sigma)[k] = sg;
+      sum += sg;
       ++kept;
     }
     out->n_slices = kept;
     out->mean_slice_sigma_gamma = kept ? sum / kept : 0.0;
   }
   return out->nan_flag ? PIC_ENUMERIC : PIC_OK;
+}
+}  // namespace
+
+int pic_diagnostics(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out) {
+  return diag_run(x, req, out, nullptr, nullptr);
+}
+
+int pic_diagnostics_slices(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out, double* sigma_gamma,
+                           double* count, int32_t cap, int32_t* n_total) {
+  if (!x || !req || !out || !n_total || cap < 0 || (cap > 0 && (!sigma_gamma || !count))) return PIC_EINVAL;
+  std::vector<double> sg, cn;
+  const int rc = diag_run(x, req, out, &sg, &cn);
+  *n_total = (int32_t)sg.size();
+  const int n = std::min<int>((int)sg.size(), cap);
+  for (int k = 0; k < n; ++k) {
+    sigma_gamma[k] = sg[k];
+    count[k] = cn[k];
+  }
+  return rc;
 }
 
 int pic_free(pic_ctx* x) {

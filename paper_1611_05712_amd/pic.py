@@ -27,6 +27,9 @@ EXPORTED = (
     "pic_num_particles", "pic_get_particles", "pic_get_state", "pic_free", "pic_strerror",
     "pic_fft_z", "pic_dht_gemm", "pic_timing_enable", "pic_timing_read",
     "pic_get_tuning", "pic_set_tuning", "pic_step_graph", "pic_batch_step", "pic_autotune",
+    "pic_diagnostics_slices",
+    "pic_mlp_num_params", "pic_mlp_workspace_bytes", "pic_mlp_init", "pic_mlp_forward", "pic_mlp_loss_grad",
+    "pic_mlp_train", "pic_mlp_get_params", "pic_mlp_set_params", "pic_mlp_steps", "pic_mlp_sync", "pic_mlp_free",
 )
 TIMERS = ("gather_push", "sort", "deposit", "fft_fwd", "dht_fwd", "psatd", "dht_inv", "fft_inv",
           "window", "scan", "dep_plan", "dep_combine", "pack")
@@ -76,6 +79,16 @@ class pic_diag_out(ctypes.Structure):
                 ("n_slices", ctypes.c_int32), ("nan_flag", ctypes.c_int32)]
 
 
+class pic_mlp_config(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("hidden", ctypes.c_int32), ("n_hidden_layers", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("prec", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+class pic_adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -98,6 +111,8 @@ def load(path: str = LIB_PATH):
         getattr(L, name).argtypes = [vp]
     L.pic_step.argtypes = [vp, i32]
     L.pic_diagnostics.argtypes = [vp, ctypes.POINTER(pic_diag_req), ctypes.POINTER(pic_diag_out)]
+    L.pic_diagnostics_slices.argtypes = [vp, ctypes.POINTER(pic_diag_req), ctypes.POINTER(pic_diag_out), _dp, _dp,
+                                         i32, ctypes.POINTER(ctypes.c_int32)]
     L.pic_get_field.argtypes = [vp, i32, i32, i32, vp]
     L.pic_set_field.argtypes = [vp, i32, i32, vp]
     L.pic_num_particles.argtypes = [vp, ctypes.POINTER(i64)]
@@ -114,6 +129,18 @@ def load(path: str = LIB_PATH):
     L.pic_step_graph.argtypes = [vp, i32]
     L.pic_batch_step.argtypes = [ctypes.POINTER(vp), i32, i32]
     L.pic_autotune.argtypes = [vp, i32, ctypes.POINTER(pic_tuning), ctypes.POINTER(ctypes.c_double)]
+    cfgp = ctypes.POINTER(pic_mlp_config)
+    L.pic_mlp_num_params.argtypes = [cfgp, ctypes.POINTER(i64)]
+    L.pic_mlp_workspace_bytes.argtypes = [cfgp, ctypes.POINTER(ctypes.c_size_t)]
+    L.pic_mlp_init.argtypes = [cfgp, _fp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.pic_mlp_forward.argtypes = [vp, vp, i32, vp]
+    L.pic_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp]
+    L.pic_mlp_train.argtypes = [vp, vp, vp, i32, vp, i32, i32, ctypes.POINTER(pic_adam), vp]
+    L.pic_mlp_get_params.argtypes = [vp, _fp]
+    L.pic_mlp_set_params.argtypes = [vp, _fp]
+    L.pic_mlp_steps.argtypes = [vp, ctypes.POINTER(i64)]
+    L.pic_mlp_sync.argtypes = [vp]
+    L.pic_mlp_free.argtypes = [vp]
     for name in EXPORTED:
         if name != "pic_strerror":
             getattr(L, name).restype = ctypes.c_int
@@ -284,6 +311,28 @@ class Simulation:
         if not (rc == PIC_OK or (allow_nan and rc == PIC_ENUMERIC)):
             _check(rc, "pic_diagnostics")
         return {f: getattr(out, f) for f, _ in pic_diag_out._fields_}
+
+    def diagnostics_slices(self, species, slice_len: float, n_sigma: float = 3.0, min_per_slice: int = 10,
+                           allow_nan: bool = False):
+        """pic_diagnostics plus per-slice rms gamma and counts: returns
+        (moments dict, sigma_gamma[n], count[n]); slice k covers
+        xi in [(k - n/2) L, (k - n/2 + 1) L)."""
+        k = self.species_names.index(species) if isinstance(species, str) else int(species)
+        req = pic_diag_req(k, slice_len, n_sigma, min_per_slice)
+        out = pic_diag_out()
+        n = ctypes.c_int32()
+        rc = self._L.pic_diagnostics_slices(self._ctx, ctypes.byref(req), ctypes.byref(out), None, None, 0,
+                                            ctypes.byref(n))
+        if not (rc == PIC_OK or (allow_nan and rc == PIC_ENUMERIC)):
+            _check(rc, "pic_diagnostics_slices")
+        sg = np.zeros(max(n.value, 1))
+        cnt = np.zeros(max(n.value, 1))
+        rc = self._L.pic_diagnostics_slices(self._ctx, ctypes.byref(req), ctypes.byref(out),
+                                            sg.ctypes.data_as(_dp), cnt.ctypes.data_as(_dp), n.value,
+                                            ctypes.byref(n))
+        if not (rc == PIC_OK or (allow_nan and rc == PIC_ENUMERIC)):
+            _check(rc, "pic_diagnostics_slices")
+        return {f: getattr(out, f) for f, _ in pic_diag_out._fields_}, sg[:n.value], cnt[:n.value]
 
     def timing_enable(self, on: bool = True):
         _check(self._L.pic_timing_enable(self._ctx, int(bool(on))), "pic_timing_enable")

@@ -15,9 +15,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "pic.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pic_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(pic_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -90,6 +94,29 @@ def test_null_arguments(lib):
     assert lib.pic_fft_z(None, 1, 64, 0, None) == pic.PIC_EINVAL
     assert lib.pic_fft_z(ctypes.c_void_p(8), 1, 48, 0, None) == pic.PIC_EINVAL
     assert lib.pic_dht_gemm(None, None, None, 1, 64, 128, 0, None) == pic.PIC_EINVAL
+
+
+def _mlp_cfg(**kw):
+    base = dict(n_in=5, hidden=128, n_hidden_layers=4, n_out=2, prec=1, max_batch=256)
+    base.update(kw)
+    return pic.pic_mlp_config(**base)
+
+
+def test_mlp_sizes_and_validation(lib):
+    n = ctypes.c_int64()
+    assert lib.pic_mlp_num_params(ctypes.byref(_mlp_cfg()), ctypes.byref(n)) == pic.PIC_OK
+    assert n.value == 5 * 128 + 128 + 3 * (128 * 128 + 128) + 128 * 2 + 2
+    b = ctypes.c_size_t()
+    assert lib.pic_mlp_workspace_bytes(ctypes.byref(_mlp_cfg()), ctypes.byref(b)) == pic.PIC_OK
+    assert b.value > 4 * 4 * n.value
+    for bad in (dict(n_in=0), dict(hidden=2000), dict(n_hidden_layers=0), dict(n_out=65), dict(prec=2),
+                dict(max_batch=0)):
+        assert lib.pic_mlp_workspace_bytes(ctypes.byref(_mlp_cfg(**bad)), ctypes.byref(b)) == pic.PIC_EINVAL
+    ctx = ctypes.c_void_p()
+    assert lib.pic_mlp_init(ctypes.byref(_mlp_cfg()), None, None, 0, None, ctypes.byref(ctx)) == pic.PIC_EINVAL
+    for name in ("pic_mlp_sync", "pic_mlp_free"):
+        assert getattr(lib, name)(None) == pic.PIC_EINVAL
+    assert lib.pic_mlp_forward(None, None, 1, None) == pic.PIC_EINVAL
 
 
 def test_strerror_covers_codes(lib):

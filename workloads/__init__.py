@@ -303,3 +303,40 @@ def random_particles(n: int, nz: int, nr: int, dz: float, dr: float, zmin: float
         "uz": (u_scale * rng.standard_normal(n)).astype(np.float32),
         "w": rng.uniform(0.5, 1.5, n).astype(np.float32),
     }
+
+
+# ---------------------------------------------------------------------------
+# surrogate network: initial parameters and minibatch order
+# ---------------------------------------------------------------------------
+def mlp_layer_sizes(n_in: int = 5, hidden: int = 128, n_hidden_layers: int = 4,
+                    n_out: int = 2) -> List[Tuple[int, int]]:
+    """(in, out) of every layer of the surrogate network."""
+    dims = [n_in] + [hidden] * n_hidden_layers + [n_out]
+    return list(zip(dims[:-1], dims[1:]))
+
+
+def mlp_init(sizes, seed: int = 0) -> np.ndarray:
+    """Flat float32 parameters, layer by layer (W_l [out][in], then b_l), each
+    drawn uniformly from +-1/sqrt(in) of its layer."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for (i, n) in sizes:
+        bound = 1.0 / math.sqrt(i)
+        parts.append(rng.uniform(-bound, bound, n * i))
+        parts.append(rng.uniform(-bound, bound, n))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def minibatch_indices(n_data: int, batch: int, steps: int, seed: int = 0) -> np.ndarray:
+    """Row indices of `steps` minibatches of `batch` rows (int32), drawn as
+    consecutive slices of fresh random permutations of the data set (rows
+    repeat within a batch only when batch > n_data)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    need = steps * batch
+    out = []
+    have = 0
+    while have < need:
+        p = rng.permutation(n_data)
+        out.append(p)
+        have += p.size
+    return np.concatenate(out)[:need].astype(np.int32)
