@@ -84,12 +84,16 @@ def _phase_units(name, wl, n_part, prec):
     return None
 
 
-def _kernel_sources_hash():
+# sources each measured kernel is built from: its traffic record stays valid
+# while these files are unchanged
+KERNEL_SOURCES = {"deposit": ("deposit.hip", "common.h", "launch.h")}
+
+
+def _kernel_sources_hash(kernel="deposit"):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1611_05712_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -105,7 +109,7 @@ def _traffic(kernel, workload):
     except Exception:
         return None
     e = d.get(workload, {}).get(kernel)
-    if not e or e.get("sources") != _kernel_sources_hash():
+    if not e or kernel not in KERNEL_SOURCES or e.get("sources") != _kernel_sources_hash(kernel):
         return None
     return round(e["bytes_per_launch"] / 1e9, 4)
 
