@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__
 DepositShape deposit_shape(int nz, int nr, int nmodes, int halo, int64_t cap) {
   DepositShape d;
   d.TZ = kTZ;
-  d.TR = nmodes <= 2 ? 16 : 8;
+  d.TR = nmodes <= 1 ? 16 : 8;
   d.halo = halo;
   d.ntz = nz / d.TZ;
   d.ntr = (nr + 1 + d.TR - 1) / d.TR;   // key columns 0..nr
@@ -639,7 +639,7 @@ static void launch_dep_h(const Parts& p, const int* offset, int* nchunk, int* ch
                          int stages, hipStream_t s) {
   switch (g.nmodes) {
     case 1: launch_dep<16, H, 1>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
-    case 2: launch_dep<16, H, 2>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
+    case 2: launch_dep<8, H, 2>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
     case 3: launch_dep<8, H, 3>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
     default: launch_dep<8, H, 4>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
   }

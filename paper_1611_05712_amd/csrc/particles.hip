@@ -196,8 +196,16 @@ template <int M>
 __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __restrict__ gf, Grid g, SpeciesConst sc,
                                                      const DevState* __restrict__ st, uint32_t* __restrict__ key,
                                                      int* __restrict__ count) {
-  const int base = blockIdx.x * (kPushPer * 256) + threadIdx.x;
   const int n = st->n_part;
+  // XCD-aware order: the hardware deals workgroups round-robin over the 8
+  // XCDs; each XCD gets one contiguous range of the active blocks, so the
+  // field nodes shared by neighbouring particles stay in one L2
+  const int nact = (n + kPushPer * 256 - 1) / (kPushPer * 256);
+  const int bx = blockIdx.x;
+  if (bx >= nact) return;
+  const int q8 = nact >> 3, r8 = nact & 7, x8 = bx & 7;
+  const int lb = x8 * q8 + min(x8, r8) + (bx >> 3);
+  const int base = lb * (kPushPer * 256) + threadIdx.x;
   const double zmin = st->zmin;
   const bool kill = g.moving_window && st->n_shift > 0;
   PushRec r[kPushPer];
