@@ -118,6 +118,13 @@ typedef struct {
   int32_t ppc_z, ppc_r, ppc_t;
   double density;     /* injected lattice density (units of n0) */
   int32_t diag;       /* 1: species selectable by pic_diagnostics */
+  int32_t self_field; /* 1 (mobile, cold, monoenergetic beams): pic_init adds the beam's
+                         own field, the field of its charge moving rigidly at its mean
+                         velocity along z: phi = rho / (k_perp^2 + [k_z]^2 / gamma^2),
+                         E = -grad phi with E_z scaled by 1/gamma^2, B_+ = -i beta E_+,
+                         B_- = +i beta E_-, B_z = 0 (spectral operators of Eqs. (2a)-(2b));
+                         it satisfies the discrete Gauss law.  0: the species starts with
+                         no field of its own */
   const double *x, *y, *z;            /* host, length n */
   const float *ux, *uy, *uz, *w;      /* host, length n; u = gamma beta (u_z is widened
                                          to FP64 on the device); w = macro-particle weight */

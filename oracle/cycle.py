@@ -82,6 +82,35 @@ class OracleSim:
         self.J = None
         self.rho_old = None
         self.rho_new = None
+        for s in wl.species:
+            if getattr(s, "self_field", False) and s.mobile and s.x.size:
+                self.add_beam_field(s)
+
+    def add_beam_field(self, s):
+        """Add the field of a cold beam's charge moving rigidly along z at its
+        weighted mean u_z (relativistic spectral Poisson equation): phi =
+        rho / (k_perp^2 + [k_z]^2 / gamma^2), E = -grad phi with E_z scaled by
+        1 / gamma^2 (Eq. (2a)), B_theta = beta E_r, i.e. B_+ = -i beta E_+,
+        B_- = +i beta E_-, B_z = 0."""
+        w = s.w.astype(np.float64)
+        ubar = float((w * s.uz.astype(np.float64)).sum() / w.sum())
+        gam = np.sqrt(1.0 + ubar * ubar)
+        beta = ubar / gam
+        rho = pt.deposit_rho(self.M, s.q * w, s.x.astype(np.float64), s.y.astype(np.float64),
+                             s.z.astype(np.float64), self.grid())
+        for m in range(self.M):
+            hk = self.hankel[m]
+            kp = hk.k[:, None]
+            phi = hk.forward(rho[m], m) / (kp ** 2 + self.kzm ** 2 / gam ** 2)
+            g = sp.grad(phi, kp, self.kzm)
+            E = (-g[0], -g[1], -g[2] / gam ** 2)
+            B = (-1j * beta * E[0], 1j * beta * E[1], np.zeros_like(phi))
+            nus = sp.hankel_orders(m)
+            for c in range(3):
+                self.Eh[m, c] += E[c]
+                self.Bh[m, c] += B[c]
+                self.E[m, c] = hk.backward(self.Eh[m, c], nus[c])
+                self.B[m, c] = hk.backward(self.Bh[m, c], nus[c])
 
     # -- helpers -----------------------------------------------------------
     def set_fields(self, E=None, B=None):

@@ -1,0 +1,120 @@
+"""The paper's accuracy study on one GPU: the same beam-plasma set-up run at
+several stencil orders for 35 mm, each compared with the infinite-order run
+(Sec. "Accurate modeling of plasma accelerators in finite order PSATD",
+Eqs. (11)-(13)).
+
+    python -m paper_1611_05712_amd.accuracy --orders 4 8 0 --out DIR
+    python -m paper_1611_05712_amd.accuracy --report DIR
+
+A run writes DIR/run_p<order>.json (witness and drive moments and the witness
+slice energy spreads at regular marks) and DIR/ez_p<order>.npy (the final
+on-grid E_z of mode 0); the report computes Err_sigma_gamma (Eq. (11), slices
+matched by offset from the centroid), Err_eps (Eq. (12), on eps_n,x) and the
+normalized form of Err_Ez (Eq. (13)) of every finite order against p = inf.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from .pic import Simulation
+from .scan import SLICE_LEN, err_sigma_gamma
+
+WITNESS_OFFSET = 4.463      # 1/k_p (75 um): the accelerating phase near the back of the first bubble
+
+
+def _state(sim, name):
+    d, sg, cnt = sim.diagnostics_slices(name, slice_len=SLICE_LEN, allow_nan=True)
+    out = {k: d[k] for k in ("eps_nx", "eps_ny", "mean_gamma", "sigma_gamma", "mean_slice_sigma_gamma", "z_mean",
+                             "sigma_z", "n", "n_slices", "nan_flag")}
+    out["slice_sigma_gamma"] = [float(v) for v in sg]
+    out["slice_count"] = [int(v) for v in cnt]
+    return out
+
+
+def run_order(order: int, steps: int, outdir: str, marks: int = 25_000, device="cuda:0", log=print,
+              witness_offset: float = WITNESS_OFFSET):
+    from workloads import paper_accuracy
+    wl = paper_accuracy(order, witness_offset)
+    t0 = time.perf_counter()
+    sim = Simulation.from_workload(wl, device=device)
+    init_s = time.perf_counter() - t0
+    del wl
+    rec = {"order": order, "steps": steps, "marks": [], "init_s": init_s}
+    done = 0
+    t0 = time.perf_counter()
+    while done < steps:
+        n = min(marks, steps - done)
+        sim.step_graph(n)
+        done += n
+        w = _state(sim, "witness")
+        dr = _state(sim, "drive")
+        el = time.perf_counter() - t0
+        rec["marks"].append({"step": done, "witness": w,
+                             "drive": {k: v for k, v in dr.items() if not k.startswith("slice_")}})
+        log(f"p={order} step {done}/{steps} ({el:.0f} s): witness <gamma> {w['mean_gamma']:.2f} "
+            f"slice sigma_gamma {w['mean_slice_sigma_gamma']:.4f} eps_nx {w['eps_nx']:.5f} n {w['n']}")
+    rec["run_s"] = time.perf_counter() - t0
+    rec["ms_per_step"] = rec["run_s"] / steps * 1e3
+    ez = sim.get_field(0, "Ez")
+    sim.close()
+    os.makedirs(outdir, exist_ok=True)
+    np.save(os.path.join(outdir, f"ez_p{order}.npy"), ez)
+    with open(os.path.join(outdir, f"run_p{order}.json"), "w") as f:
+        json.dump(rec, f)
+    return rec
+
+
+def errors(run_f, run_inf, ez_f=None, ez_inf=None, mark=-1):
+    a = run_f["marks"][mark]["witness"]
+    b = run_inf["marks"][mark]["witness"]
+    out = {"order": run_f["order"], "step": run_f["marks"][mark]["step"],
+           "err_sigma_gamma": err_sigma_gamma(a["slice_sigma_gamma"], a["slice_count"], b["slice_sigma_gamma"],
+                                              b["slice_count"]),
+           "err_eps": (a["eps_nx"] - b["eps_nx"]) / b["eps_nx"]}
+    if ez_f is not None and ez_inf is not None:
+        fa, fb = np.fft.fft2(ez_f), np.fft.fft2(ez_inf)
+        out["err_ez"] = float(np.linalg.norm(fa - fb) / np.linalg.norm(fb))
+    return out
+
+
+def report(outdir: str):
+    runs = {}
+    for f in os.listdir(outdir):
+        if f.startswith("run_p") and f.endswith(".json"):
+            r = json.load(open(os.path.join(outdir, f)))
+            runs[r["order"]] = r
+    if 0 not in runs:
+        raise SystemExit("no infinite-order run (p = 0) in " + outdir)
+    ez = {p: np.load(os.path.join(outdir, f"ez_p{p}.npy")) for p in runs
+          if os.path.exists(os.path.join(outdir, f"ez_p{p}.npy"))}
+    rows = []
+    for p in sorted(k for k in runs if k):
+        rows.append(errors(runs[p], runs[0], ez.get(p), ez.get(0)))
+    return {"rows": rows, "inf": {k: runs[0]["marks"][-1]["witness"][k]
+                                  for k in ("mean_gamma", "mean_slice_sigma_gamma", "eps_nx", "n")},
+            "ms_per_step": {p: r["ms_per_step"] for p, r in runs.items()}}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--orders", type=int, nargs="*", default=[])
+    ap.add_argument("--steps", type=int, default=175_000)
+    ap.add_argument("--marks", type=int, default=25_000)
+    ap.add_argument("--out", default="accuracy_runs")
+    ap.add_argument("--report", metavar="DIR")
+    a = ap.parse_args(argv)
+    if a.report:
+        print(json.dumps(report(a.report), indent=1))
+        return
+    for p in a.orders:
+        run_order(p, a.steps, a.out, a.marks, log=lambda m: print(m, file=sys.stderr, flush=True))
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,7 @@ int validate(const pic_config* c, const pic_species* s, int ns) {
     if (p.n > 0 && (!p.x || !p.y || !p.z || !p.w)) return PIC_EINVAL;
     if (p.n > 0 && p.mobile && (!p.ux || !p.uy || !p.uz)) return PIC_EINVAL;
     if (p.inject && (p.ppc_z < 1 || p.ppc_r < 1 || p.ppc_t < 1 || !(p.density > 0))) return PIC_EINVAL;
+    if (p.self_field && !p.mobile) return PIC_EINVAL;
   }
   return PIC_OK;
 }
@@ -562,6 +563,54 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
     PIC_CK(hipMemcpyAsync(x->bg, fld(x->real, x, kCompJ + 4, 0), M * plane * sizeof(float2),
                           hipMemcpyDeviceToDevice, s));
     launch_fill_zero(x->real, kNumComp * M * plane * sizeof(float2), s);
+  }
+
+  // -------- own fields of the beams flagged self_field: each beam alone is
+  // sorted and deposited, its rho transformed, and the field of that charge
+  // moving rigidly at the beam's mean u_z added to the spectral E, B
+  bool self_fields = false;
+  for (int i = 0; i < n_species; ++i)
+    self_fields = self_fields || (species[i].self_field && species[i].mobile && species[i].n > 0);
+  if (self_fields) {
+    Parts& P = x->parts[1];
+    for (int i = 0; i < n_species; ++i) {
+      const pic_species& p = species[i];
+      if (!p.self_field || !p.mobile || p.n == 0) continue;
+      double sw = 0.0, su = 0.0;
+      std::vector<float> qw(p.n);
+      for (int64_t k = 0; k < p.n; ++k) {
+        sw += (double)p.w[k];
+        su += (double)p.w[k] * (double)p.uz[k];
+        qw[k] = (float)(p.q * (double)p.w[k]);
+      }
+      const double ubar = sw > 0.0 ? su / sw : 0.0;
+      const double gam = sqrt(1.0 + ubar * ubar), beta = ubar / gam;
+      PIC_CK(hipMemcpyAsync(P.x, p.x, p.n * sizeof(double), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.y, p.y, p.n * sizeof(double), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.z, p.z, p.n * sizeof(double), hipMemcpyHostToDevice, s));
+      PIC_CK(hipMemcpyAsync(P.w, qw.data(), p.n * sizeof(float), hipMemcpyHostToDevice, s));
+      PIC_CK(hipStreamSynchronize(s));
+      launch_fill_zero(P.ux, cap * sizeof(float), s);
+      launch_fill_zero(P.uy, cap * sizeof(float), s);
+      launch_fill_zero(P.uz, cap * sizeof(double), s);
+      launch_fill_zero(P.sp, cap, s);
+      hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, x->st, cfg->z_min, (int)p.n);
+      launch_keys(P, g, x->st, x->key, x->count, (int)cap, s);
+      launch_scan(x->count, g.ncells + 1, x->bsum, x->offset, x->cursor, g.ncells, x->st, s);
+      launch_scatter(P, x->parts[0], x->key, x->cursor, x->st, g.ncells, (int)cap, s);
+      launch_deposit(x->parts[0], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real, nullptr,
+                     g, x->st, kDepAll, s);
+      forward_transform(x, x->real, kCompJ, kNumSrc, x->pt_fwd_src);
+      launch_beam_field(x->spec, x->kperp, x->kzm, nz, nr, M, gam, beta, s);
+    }
+    // real-space E, B and the gather copy of the initial fields
+    const float* const* tab = x->ptr_tab + x->pt_inv_eb;
+    launch_dht_gemm(tab, tab + 6 * M, (float* const*)(tab + 12 * M), 6 * M, nr, 2 * nz, cfg->hankel_prec,
+                    x->gemm_bm, s);
+    launch_fft(fld(x->tmp, x, 0, 0), fld(x->real, x, 0, 0), x->tw, nz, (int64_t)6 * M * nr, true, false, nullptr, s);
+    launch_pack_gather(x->real, x->gfield, nr, nz, M, s);
+    launch_fill_zero(fld(x->real, x, kCompJ, 0), (size_t)kNumSrc * M * plane * sizeof(float2), s);
+    launch_fill_zero(fld(x->spec, x, kCompJ, 0), (size_t)kNumSrc * M * plane * sizeof(float2), s);
   }
 
   // -------- mobile particles

@@ -149,6 +149,50 @@ __global__ __launch_bounds__(256) void k_tail_transform(const float2* __restrict
   }
 }
 
+// Own field of a cold beam moving rigidly along z with velocity beta (Lorentz
+// factor gamma), added to the spectral E, B from the beam's rho in the
+// rho^{n+1} slot: phi = rho / (k_perp^2 + [k_z]^2 / gamma^2), E = -grad phi
+// with E_z scaled by 1 / gamma^2, B_+ = -i beta E_+, B_- = +i beta E_-.
+// div E = k_perp (E_+ - E_-) + i [k_z] E_z = rho holds by construction.
+__global__ __launch_bounds__(256) void k_beam_field(float2* __restrict__ spec, const double* __restrict__ kperp,
+                                                    const double* __restrict__ kzm, int nz, int nr, int M,
+                                                    double gamma, double beta) {
+  const size_t plane = (size_t)nr * nz;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)M * plane) return;
+  const int m = (int)(idx / plane);
+  const size_t cell = idx % plane;
+  const int ik = (int)(cell / nz), iz = (int)(cell % nz);
+  const double kp = kperp[(size_t)m * nr + ik], kz = kzm[iz];
+  const double ig2 = 1.0 / (gamma * gamma);
+  const float2 rho = spec[((size_t)(kCompJ + 4) * M + m) * plane + cell];
+  const double den = kp * kp + kz * kz * ig2;
+  const double pr = rho.x / den, pi = rho.y / den;            // phi
+  const double ep_r = 0.5 * kp * pr, ep_i = 0.5 * kp * pi;    // E_+ = k_perp phi / 2
+  const double em_r = -ep_r, em_i = -ep_i;                    // E_- = -k_perp phi / 2
+  const double ez_r = kz * pi * ig2, ez_i = -kz * pr * ig2;   // E_z = -i [k_z] phi / gamma^2
+  float2* f[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) f[c] = spec + ((size_t)c * M + m) * plane + cell;
+  f[0]->x += (float)ep_r;
+  f[0]->y += (float)ep_i;
+  f[1]->x += (float)em_r;
+  f[1]->y += (float)em_i;
+  f[2]->x += (float)ez_r;
+  f[2]->y += (float)ez_i;
+  f[3]->x += (float)(beta * ep_i);                            // B_+ = -i beta E_+
+  f[3]->y += (float)(-beta * ep_r);
+  f[4]->x += (float)(-beta * em_i);                           // B_- = +i beta E_-
+  f[4]->y += (float)(beta * em_r);
+}
+
+void launch_beam_field(float2* spec, const double* kperp, const double* kzm, int nz, int nr, int M, double gamma,
+                       double beta, hipStream_t s) {
+  const size_t n = (size_t)M * nr * nz;
+  hipLaunchKernelGGL(k_beam_field, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spec, kperp, kzm, nz, nr, M,
+                     gamma, beta);
+}
+
 void launch_psatd(float2* spec, const double* kperp, const double* kzm, const float2* tw, const float2* tailhat,
                   int nz, int nr, int M, double dt, bool apply_shift, bool correct, hipStream_t s) {
   int64_t n = (int64_t)nr * nz;

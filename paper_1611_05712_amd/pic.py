@@ -61,7 +61,7 @@ class pic_species(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("q", ctypes.c_double), ("m", ctypes.c_double),
                 ("mobile", ctypes.c_int32), ("inject", ctypes.c_int32),
                 ("ppc_z", ctypes.c_int32), ("ppc_r", ctypes.c_int32), ("ppc_t", ctypes.c_int32),
-                ("density", ctypes.c_double), ("diag", ctypes.c_int32),
+                ("density", ctypes.c_double), ("diag", ctypes.c_int32), ("self_field", ctypes.c_int32),
                 ("x", _dp), ("y", _dp), ("z", _dp), ("ux", _fp), ("uy", _fp), ("uz", _fp),
                 ("w", _fp)]
 
@@ -201,7 +201,7 @@ class Simulation:
             arr[k] = pic_species(
                 x.shape[0], s.q, s.m, int(bool(s.mobile)), int(bool(getattr(s, "inject", False))),
                 ppc[0], ppc[1], ppc[2], float(getattr(s, "density", 1.0)),
-                int(bool(getattr(s, "diag", False))),
+                int(bool(getattr(s, "diag", False))), int(bool(getattr(s, "self_field", False))),
                 x.ctypes.data_as(_dp), y.ctypes.data_as(_dp), z.ctypes.data_as(_dp),
                 ux.ctypes.data_as(_fp), uy.ctypes.data_as(_fp), uz.ctypes.data_as(_fp),
                 w.ctypes.data_as(_fp))

@@ -71,7 +71,7 @@ def test_invalid_configs_rejected(lib, bad):
 
 def test_invalid_species_rejected(lib):
     arr = (pic.pic_species * 1)()
-    arr[0] = pic.pic_species(10, 0.0, 1.0, 1, 0, 1, 1, 1, 1.0, 0, None, None, None, None, None,
+    arr[0] = pic.pic_species(10, 0.0, 1.0, 1, 0, 1, 1, 1, 1.0, 0, 0, None, None, None, None, None,
                              None, None)
     rc, _ = _bytes(lib, _cfg(), arr, 1)
     assert rc == pic.PIC_EINVAL           # zero charge
@@ -134,7 +134,7 @@ def test_workload_presets_fit_the_interface(lib):
             a = [np.ascontiguousarray(getattr(s, f)) for f in ("x", "y", "z", "ux", "uy", "uz", "w")]
             keep += a
             arr[k] = pic.pic_species(s.n, s.q, s.m, int(s.mobile), int(s.inject), *s.ppc, s.density,
-                                     int(s.diag), *[v.ctypes.data_as(pic._dp) for v in a[:3]],
+                                     int(s.diag), int(s.self_field), *[v.ctypes.data_as(pic._dp) for v in a[:3]],
                                      *[v.ctypes.data_as(pic._fp) for v in a[3:]])
         cfg = _cfg(nz=wl.nz, nr=wl.nr, order=wl.order, dz=wl.dz, dr=wl.dr, dt=wl.dt, z_min=wl.zmin,
                    moving_window=int(wl.moving_window))

@@ -382,3 +382,46 @@ def test_split_precision_c0_moment_error(prec, name):
            ("mean_gamma", "sigma_gamma", "mean_slice_sigma_gamma", "eps_nx", "eps_ny")}
     print(name, {k: f"{v:.2e}" for k, v in rel.items()})
     assert max(rel.values()) < (1e-4 if prec == 0 else 1e-2), rel
+
+
+def _beam_only(gamma, n=20_000, seed=3):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0.0, 0.2, n)
+    y = rng.normal(0.0, 0.2, n)
+    z = rng.normal(3.2, 0.6, n)
+    uz = np.full(n, np.sqrt(gamma ** 2 - 1), np.float32)
+    zero = np.zeros(n, np.float32)
+    w = np.full(n, 0.05 / n, np.float32)
+    b = Species("beam", -1.0, 1.0, True, x, y, z, zero, zero.copy(), uz, w, diag=True, self_field=True)
+    return Workload("beam", 128, 32, 2, 16, 0.05, 0.05, 0.05, 0.0, False, KPERP_JM_ZEROS, 1, [b])
+
+
+@pytest.mark.parametrize("gamma", [3.0, 1000.0])
+def test_beam_self_field_at_init_matches_oracle(gamma):
+    """The beam's own field built at initialisation (relativistic spectral
+    Poisson equation) against the oracle's, before any step and after one."""
+    wl = _beam_only(gamma)
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    for m in range(2):
+        for which in ("E", "B"):
+            assert _vector_rel(sim, o, m, which) < 2e-5, (m, which)
+    sim.step(1)
+    o.step(1)
+    for m in range(2):
+        for which in ("E", "B"):
+            assert _vector_rel(sim, o, m, which) < 2e-5, (m, which)
+
+
+def test_full_cycle_with_self_field_beam_in_plasma():
+    wl = preset("small")
+    for s in wl.species:
+        if s.name == "drive":
+            s.self_field = True
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.step(2)
+    o.step(2)
+    for m in range(2):
+        for which in ("E", "B"):
+            assert _vector_rel(sim, o, m, which) < 1e-5, (m, which)

@@ -188,3 +188,50 @@ def test_c0_oracle_runs_and_stays_finite():
     out = beam_moments(s.x, s.y, s.z, s.ux, s.uy, s.uz, s.w, slice_len=0.02975)
     assert out["nan_flag"] == 0 and out["n_slices"] > 0
 
+
+
+def _beam_workload(gamma=100.0, n=200_000, sigma_r=0.2, sigma_z=1.0, seed=3):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0.0, sigma_r, n)
+    y = rng.normal(0.0, sigma_r, n)
+    z = rng.normal(3.2, sigma_z, n)
+    uz = np.full(n, np.sqrt(gamma ** 2 - 1), np.float32)
+    zero = np.zeros(n, np.float32)
+    w = np.full(n, 0.05 / n, np.float32)
+    b = Species("beam", -1.0, 1.0, True, x, y, z, zero, zero.copy(), uz, w, diag=True, self_field=True)
+    return Workload("beam", 128, 32, 2, 16, 0.05, 0.05, 0.05, 0.0, False, KPERP_JM_ZEROS, 1, [b])
+
+
+def test_beam_field_satisfies_gauss_law():
+    wl = _beam_workload(gamma=3.0, n=20_000)
+    sim = OracleSim(wl)
+    b = wl.species[0]
+    rho = pt.deposit_rho(2, b.q * b.w.astype(np.float64), b.x, b.y, b.z, sim.grid())
+    for m in range(2):
+        hk = sim.hankel[m]
+        div = sp.div(tuple(sim.Eh[m]), hk.k[:, None], sim.kzm)
+        want = hk.forward(rho[m], m)
+        assert np.abs(div - want).max() < 1e-10 * np.abs(want).max()
+        # B has no z component and no divergence
+        assert np.abs(sim.Bh[m, 2]).max() == 0
+        assert np.abs(sp.div(tuple(sim.Bh[m]), hk.k[:, None], sim.kzm)).max() < 1e-10 * np.abs(sim.Bh[m]).max()
+
+
+def test_beam_field_of_a_long_relativistic_beam_closed_form():
+    # gamma sigma_z >> sigma_r: at the beam centre the field is that of an
+    # infinitely long line charge with a Gaussian profile,
+    # E_r = lambda / (2 pi r) (1 - exp(-r^2 / 2 sigma_r^2)), B_theta = beta E_r
+    gamma, sr, sz = 100.0, 0.2, 1.0
+    wl = _beam_workload(gamma, sigma_r=sr, sigma_z=sz)
+    sim = OracleSim(wl)
+    b = wl.species[0]
+    j = int(round(3.2 / wl.dz))
+    lam = b.q * float(b.w.astype(np.float64).sum()) / (np.sqrt(2 * np.pi) * sz)
+    r = sim.hankel[0].r
+    Er = (sim.E[0, 0, :, j] + sim.E[0, 1, :, j]).real          # mode 0: E_r = E_+ + E_-
+    Bt = (1j * (sim.B[0, 0, :, j] - sim.B[0, 1, :, j])).real    # B_theta = i (B_+ - B_-)
+    want = lam / (2 * np.pi * r) * (1 - np.exp(-r ** 2 / (2 * sr ** 2)))
+    sel = (r > 0.1) & (r < 1.0)
+    assert np.abs(Er[sel] - want[sel]).max() < 0.02 * np.abs(want).max()
+    beta = np.sqrt(1 - 1 / gamma ** 2)
+    np.testing.assert_allclose(Bt, beta * Er, rtol=0, atol=1e-10 * np.abs(Er).max())

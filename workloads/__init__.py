@@ -63,6 +63,7 @@ class Species:
     ppc: Tuple[int, int, int] = (2, 2, 4)
     density: float = 1.0     # lattice density in units of n0 (for injection)
     diag: bool = False       # beam species reported by the diagnostics
+    self_field: bool = False  # start with the beam's own (rigidly moving) space-charge field
 
     @property
     def n(self) -> int:
@@ -159,9 +160,9 @@ def _plasma_species(nz, nr, dz, dr, zmin, ppc=(2, 2, 4)):
     return ele, ion
 
 
-def _bunch_species(name, n, charge_C, gamma, sigma_r, sigma_z, zc, seed, diag):
+def _bunch_species(name, n, charge_C, gamma, sigma_r, sigma_z, zc, seed, diag, self_field=False):
     b = gaussian_bunch(n, charge_C, gamma, sigma_r, sigma_z, zc, seed)
-    return Species(name, -1.0, 1.0, True, diag=diag, **b)
+    return Species(name, -1.0, 1.0, True, diag=diag, self_field=self_field, **b)
 
 
 def preset(name: str, seed: int = 0) -> Workload:
@@ -207,6 +208,42 @@ def preset(name: str, seed: int = 0) -> Workload:
         return Workload("small", nz, nr, 2, 16, dz, dr, dz, zmin, True, KPERP_JM_ZEROS, 10,
                         [ele, ion, drive])
     raise KeyError(name)
+
+
+# ---------------------------------------------------------------------------
+# the paper's accuracy set-up (Sec. "Accurate modeling of plasma accelerators
+# in finite order PSATD")
+# ---------------------------------------------------------------------------
+M_E_MEV = 0.51099895000
+UM = 1e-6 * 5.9507e4        # one micrometre in 1/k_p at n0 = 1e17 cm^-3 (k_p = 5.9507e4 1/m)
+PAPER_DZ = 0.2 * UM         # 5 cells per micrometre along z
+PAPER_DR = UM / 1.5         # 1.5 cells per micrometre along r
+PAPER_STEPS = 175_000       # 35 mm of propagation at dt = dz / c
+
+
+def paper_accuracy(order: int, witness_offset: float, seed: int = 0, n_drive: int = 1_000_000,
+                   n_witness: int = 200_000, nz: int = 1024, nr: int = 320,
+                   self_field: bool = True) -> Workload:
+    """Cold 1 GeV, 180 pC drive (8.4 um rms length, 5 um rms width) and cold
+    25 MeV, 50 pC witness (2 um, 1 um) in a 1e17 cm^-3 plasma, 2x2x4 particles
+    per cell, two modes, dt = dz/c, moving window.  The box is the paper's
+    900 x 300 cells rounded up to 1024 x 320 (the FFT length and the radial tile
+    size); the drive sits at 3/4 of the box, the witness `witness_offset`
+    (1/k_p) behind it.  Both beams start with their own space-charge field
+    (`self_field`)."""
+    zmin = 0.0
+    ele, ion = _plasma_species(nz, nr, PAPER_DZ, PAPER_DR, zmin)
+    zd = zmin + 0.75 * nz * PAPER_DZ
+    g_drive = 1.0 + 1000.0 / M_E_MEV
+    g_wit = 1.0 + 25.0 / M_E_MEV
+    drive = _bunch_species("drive", n_drive, 180e-12, g_drive, 5.0 * UM, 8.4 * UM, zd, seed, True,
+                           self_field)
+    species = [ele, ion, drive]
+    if n_witness:
+        species.append(_bunch_species("witness", n_witness, 50e-12, g_wit, 1.0 * UM, 2.0 * UM,
+                                      zd - witness_offset, seed + 1, True, self_field))
+    return Workload(f"paper_p{order}", nz, nr, 2, order, PAPER_DZ, PAPER_DR, PAPER_DZ, zmin, True,
+                    KPERP_JM_ZEROS, PAPER_STEPS, species)
 
 
 # ---------------------------------------------------------------------------
