@@ -60,6 +60,7 @@ class OracleSim:
         self.order = wl.order
         self.moving_window = wl.moving_window
         self.correct = current_correction
+        self.filter = int(getattr(wl, "filter", 0))
         self.n_shift = 0
         self.hankel = [sp.HankelPair(m, wl.nr, wl.dr, wl.kperp_grid) for m in range(self.M)]
         self.kzm = sp.kz_modified(sp.kz_grid(wl.nz, wl.dz), wl.dz, wl.order)[None, :]
@@ -173,6 +174,10 @@ class OracleSim:
             Jh = tuple(hk.forward(self.J[m, c], nus[c]) for c in range(3))
             r0 = hk.forward(self.rho_old[m], m)
             r1 = hk.forward(self.rho_new[m], m)
+            if self.filter:
+                f = sp.binomial_filter(self.kz, self.dz, hk.k, self.dr)
+                Jh = tuple(f * j for j in Jh)
+                r0, r1 = f * r0, f * r1
             if self.correct:
                 Jh = sp.current_correction(Jh, r0, r1, self.dt, kp, self.kzm)
             En, Bn = sp.psatd_push(tuple(self.Eh[m]), tuple(self.Bh[m]), Jh, r0, r1, self.dt, kp, self.kzm)

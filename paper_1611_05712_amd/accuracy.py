@@ -10,7 +10,9 @@ A run writes DIR/run_p<order>.json (witness and drive moments and the witness
 slice energy spreads at regular marks) and DIR/ez_p<order>.npy (the final
 on-grid E_z of mode 0); the report computes Err_sigma_gamma (Eq. (11), slices
 matched by offset from the centroid), Err_eps (Eq. (12), on eps_n,x) and the
-normalized form of Err_Ez (Eq. (13)) of every finite order against p = inf.
+normalized form of Err_Ez (Eq. (13)) of every finite order against p = inf,
+and locates the numerical Cherenkov excess in the E_z spectrum against the
+resonance of Eq. (10) for the drive beam.
 """
 from __future__ import annotations
 
@@ -38,14 +40,15 @@ def _state(sim, name):
 
 
 def run_order(order: int, steps: int, outdir: str, marks: int = 25_000, device="cuda:0", log=print,
-              witness_offset: float = WITNESS_OFFSET):
+              witness_offset: float = WITNESS_OFFSET, witness_mev: float = 25.0, filter: int = 0):
     from workloads import paper_accuracy
-    wl = paper_accuracy(order, witness_offset)
+    wl = paper_accuracy(order, witness_offset, witness_mev=witness_mev, filter=filter)
     t0 = time.perf_counter()
     sim = Simulation.from_workload(wl, device=device)
     init_s = time.perf_counter() - t0
     del wl
-    rec = {"order": order, "steps": steps, "marks": [], "init_s": init_s}
+    rec = {"order": order, "steps": steps, "marks": [], "init_s": init_s, "witness_mev": witness_mev,
+           "filter": filter}
     done = 0
     t0 = time.perf_counter()
     while done < steps:
@@ -68,6 +71,55 @@ def run_order(order: int, steps: int, outdir: str, marks: int = 25_000, device="
     with open(os.path.join(outdir, f"run_p{order}.json"), "w") as f:
         json.dump(rec, f)
     return rec
+
+
+def modified_kz(kz, dz: float, order: int):
+    """[k_z] of Eq. (5), sum_j alpha_{n,j} sin(k_z j dz) / (j dz) with p = 2n; the
+    coefficients of Eq. (3) by their ratio alpha_{n,j+1}/alpha_{n,j} =
+    -(n - j)/(n + j + 1) from alpha_{n,1} = 2n/(n + 1).  order 0: k_z itself."""
+    kz = np.asarray(kz, np.float64)
+    if order == 0:
+        return kz.copy()
+    n = order // 2
+    a = 2.0 * n / (n + 1.0)
+    out = np.zeros_like(kz)
+    for j in range(1, n + 1):
+        out += a * np.sin(kz * j * dz) / (j * dz)
+        a *= -(n - j) / (n + j + 1.0)
+    return out
+
+
+def resonance_kz(gamma: float, order: int, dz: float) -> float:
+    """On-axis (k_perp = 0) numerical Cherenkov resonance of Eq. (10): the
+    smallest k_z in (0, pi/dz) where the numerical phase velocity [k_z]/k_z
+    drops to the beam speed; NaN when there is none (infinite order)."""
+    beta = np.sqrt(1.0 - 1.0 / gamma ** 2)
+    k = np.linspace(1e-6, np.pi / dz, 200_001)
+    f = modified_kz(k, dz, order) / k - beta
+    idx = np.nonzero(np.sign(f[:-1]) != np.sign(f[1:]))[0]
+    if idx.size == 0:
+        return float("nan")
+    lo, hi = k[idx[0]], k[idx[0] + 1]
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if np.sign(modified_kz(np.array([mid]), dz, order)[0] / mid - beta) == np.sign(f[idx[0]]):
+            lo = mid
+        else:
+            hi = mid
+    return float(0.5 * (lo + hi))
+
+
+def ez_excess_peak(ez_f, ez_inf, dz: float, rows: int):
+    """k_z at which the z-spectrum of E_z (mode 0, averaged over the first
+    `rows` radial rows) most exceeds that of the infinite-order run."""
+    sf = np.abs(np.fft.fft(ez_f[:rows], axis=-1)).mean(axis=0)
+    si = np.abs(np.fft.fft(ez_inf[:rows], axis=-1)).mean(axis=0)
+    nz = ez_f.shape[-1]
+    kz = 2.0 * np.pi * np.fft.fftfreq(nz, dz)
+    sel = (kz > 0.05 * np.pi / dz)
+    ratio = np.where(sel, sf / np.maximum(si, 1e-30 * si.max()), 0.0)
+    i = int(np.argmax(ratio))
+    return float(kz[i]), float(ratio[i])
 
 
 def errors(run_f, run_inf, ez_f=None, ez_inf=None, mark=-1):
@@ -93,9 +145,17 @@ def report(outdir: str):
         raise SystemExit("no infinite-order run (p = 0) in " + outdir)
     ez = {p: np.load(os.path.join(outdir, f"ez_p{p}.npy")) for p in runs
           if os.path.exists(os.path.join(outdir, f"ez_p{p}.npy"))}
+    from workloads import PAPER_DZ, M_E_MEV
+    g_drive = 1.0 + 1000.0 / M_E_MEV
     rows = []
     for p in sorted(k for k in runs if k):
-        rows.append(errors(runs[p], runs[0], ez.get(p), ez.get(0)))
+        e = errors(runs[p], runs[0], ez.get(p), ez.get(0))
+        if p in ez and 0 in ez:
+            kpk, ratio = ez_excess_peak(ez[p], ez[0], PAPER_DZ, ez[p].shape[0] // 8)
+            e["ez_excess_kz_dz"] = kpk * PAPER_DZ
+            e["ez_excess_ratio"] = ratio
+            e["resonance_kz_dz_drive"] = resonance_kz(g_drive, p, PAPER_DZ) * PAPER_DZ
+        rows.append(e)
     return {"rows": rows, "inf": {k: runs[0]["marks"][-1]["witness"][k]
                                   for k in ("mean_gamma", "mean_slice_sigma_gamma", "eps_nx", "n")},
             "ms_per_step": {p: r["ms_per_step"] for p, r in runs.items()}}
@@ -107,13 +167,18 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=175_000)
     ap.add_argument("--marks", type=int, default=25_000)
     ap.add_argument("--out", default="accuracy_runs")
+    ap.add_argument("--witness-mev", type=float, default=25.0,
+                    help="witness kinetic energy (the paper's set-up: 25 MeV)")
+    ap.add_argument("--filter", type=int, default=0, choices=[0, 1],
+                    help="binomial J/rho filter passes (pic_config.filter)")
     ap.add_argument("--report", metavar="DIR")
     a = ap.parse_args(argv)
     if a.report:
         print(json.dumps(report(a.report), indent=1))
         return
     for p in a.orders:
-        run_order(p, a.steps, a.out, a.marks, log=lambda m: print(m, file=sys.stderr, flush=True))
+        run_order(p, a.steps, a.out, a.marks, log=lambda m: print(m, file=sys.stderr, flush=True),
+                  witness_mev=a.witness_mev, filter=a.filter)
 
 
 if __name__ == "__main__":

@@ -159,6 +159,7 @@ int validate(const pic_config* c, const pic_species* s, int ns) {
   if (c->moving_window && fabs(c->dt - c->dz) > 1e-12 * c->dz) return PIC_EINVAL;
   if (c->kperp_grid < 0 || c->kperp_grid > 2) return PIC_EINVAL;
   if (c->hankel_prec < 0 || c->hankel_prec > 2) return PIC_EINVAL;
+  if (c->filter < 0 || c->filter > 1) return PIC_EINVAL;
   if (ns < 0 || ns > kMaxSpecies || (ns > 0 && !s)) return PIC_EINVAL;
   for (int i = 0; i < ns; ++i) {
     const pic_species& p = s[i];
@@ -716,7 +717,7 @@ int pic_spectral_push(pic_ctx* x) {
   {
     Phase ph(x, PIC_T_PSATD);
     launch_psatd(x->spec, x->kperp, x->kzm, x->tw, x->tailhat, nz, nr, M, x->cfg.dt, apply_shift,
-                 x->cfg.current_correction != 0, s);
+                 x->cfg.current_correction != 0, x->kz, x->cfg.dz, x->cfg.dr, x->cfg.filter, s);
   }
   x->spec_pending = false;
   {

@@ -73,7 +73,8 @@ int gemm_tile_bm(int n, int pref_bm);
 void launch_dht_gemm(const float* const* at, const float* const* x, float* const* y, int batch, int n, int ncols,
                      int prec, int pref_bm, hipStream_t s);
 void launch_psatd(float2* spec, const double* kperp, const double* kzm, const float2* tw, const float2* tailhat,
-                  int nz, int nr, int M, double dt, bool apply_shift, bool correct, hipStream_t s);
+                  int nz, int nr, int M, double dt, bool apply_shift, bool correct, const double* kz_grid, double dz,
+                  double dr, int filter, hipStream_t s);
 void launch_beam_field(float2* spec, const double* kperp, const double* kzm, int nz, int nr, int M, double gamma,
                        double beta, hipStream_t s);
 void launch_tail_transform(const float2* tail, float2* tailhat, const float* const* ft_of_row, int nr, int nrows,

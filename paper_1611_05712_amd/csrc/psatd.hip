@@ -48,7 +48,8 @@ __device__ __forceinline__ Coef make_coef(double kp, double kz, double dt) {
 __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const double* __restrict__ kperp,
                                                const double* __restrict__ kzm, const float2* __restrict__ tw,
                                                const float2* __restrict__ tailhat, int nz, int nr, int M, double dt,
-                                               int apply_shift, int correct) {
+                                               int apply_shift, int correct, const double* __restrict__ kz_grid,
+                                               double dz, double dr, int filter) {
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= (int64_t)nr * nz) return;
   const int ik = (int)(cell / nz);
@@ -78,6 +79,15 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
       J[c] = *f[6 + c];
     }
     float2 r0 = *f[9], r1 = *f[10];
+    if (filter) {
+      // one binomial (1/4, 1/2, 1/4) pass along z and along r, in spectral form
+      const double cz = cos(0.5 * kz_grid[iz] * dz), cr = cos(0.5 * kpd * dr);
+      const float fs = (float)(cz * cz * cr * cr);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) J[c] = cscale(J[c], fs);
+      r0 = cscale(r0, fs);
+      r1 = cscale(r1, fs);
+    }
     if (apply_shift) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -194,10 +204,11 @@ void launch_beam_field(float2* spec, const double* kperp, const double* kzm, int
 }
 
 void launch_psatd(float2* spec, const double* kperp, const double* kzm, const float2* tw, const float2* tailhat,
-                  int nz, int nr, int M, double dt, bool apply_shift, bool correct, hipStream_t s) {
+                  int nz, int nr, int M, double dt, bool apply_shift, bool correct, const double* kz_grid, double dz,
+                  double dr, int filter, hipStream_t s) {
   int64_t n = (int64_t)nr * nz;
   hipLaunchKernelGGL(k_psatd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spec, kperp, kzm, tw, tailhat, nz,
-                     nr, M, dt, apply_shift ? 1 : 0, correct ? 1 : 0);
+                     nr, M, dt, apply_shift ? 1 : 0, correct ? 1 : 0, kz_grid, dz, dr, filter);
 }
 
 void launch_tail_transform(const float2* tail, float2* tailhat, const float* const* ft_of_row, int nr, int nrows,

@@ -46,7 +46,8 @@ class pic_config(ctypes.Structure):
                 ("order", ctypes.c_int32), ("dz", ctypes.c_double), ("dr", ctypes.c_double),
                 ("dt", ctypes.c_double), ("z_min", ctypes.c_double),
                 ("moving_window", ctypes.c_int32), ("kperp_grid", ctypes.c_int32),
-                ("hankel_prec", ctypes.c_int32), ("current_correction", ctypes.c_int32)]
+                ("hankel_prec", ctypes.c_int32), ("current_correction", ctypes.c_int32),
+                ("filter", ctypes.c_int32)]
 
 
 class pic_tuning(ctypes.Structure):
@@ -177,13 +178,13 @@ class Simulation:
 
     def __init__(self, nz, nr, n_modes, order, dz, dr, dt, z_min, species: Sequence,
                  moving_window=False, kperp_grid=KPERP_JM_ZEROS, hankel_prec=H_FP32,
-                 current_correction=True, max_particles=0, device="cuda:0", stream=None):
+                 current_correction=True, max_particles=0, device="cuda:0", stream=None, filter=0):
         import torch
         L = load()
         self._L = L
         self.device = torch.device(device)
         self.cfg = pic_config(nz, nr, n_modes, order, dz, dr, dt, z_min, int(bool(moving_window)),
-                              kperp_grid, hankel_prec, int(bool(current_correction)))
+                              kperp_grid, hankel_prec, int(bool(current_correction)), int(filter))
         self.nz, self.nr, self.n_modes = nz, nr, n_modes
         self.species_names = [s.name for s in species]
         self._keep = []
@@ -223,6 +224,7 @@ class Simulation:
 
     @classmethod
     def from_workload(cls, wl, **kw):
+        kw.setdefault("filter", getattr(wl, "filter", 0))
         return cls(wl.nz, wl.nr, wl.n_modes, wl.order, wl.dz, wl.dr, wl.dt, wl.zmin, wl.species,
                    moving_window=wl.moving_window, kperp_grid=wl.kperp_grid, **kw)
 

@@ -42,3 +42,28 @@ def test_errors_of_a_run_against_its_twin():
     ez = rng.standard_normal((8, 16)) + 1j * rng.standard_normal((8, 16))
     e = errors(f, ref, ez * 1.01, ez)
     assert e["err_ez"] == pytest.approx(0.01, rel=1e-12)
+
+
+@pytest.mark.parametrize("order", [4, 8, 16, 32, 64])
+def test_report_resonance_matches_oracle(order):
+    # the report's own [k_z] and resonance root against the oracle's
+    from oracle import spectral as sp
+    from oracle import stencil as st
+    from paper_1611_05712_amd.accuracy import modified_kz, resonance_kz
+    dz = 0.0119
+    kz = np.linspace(0.1, np.pi / dz, 50)
+    np.testing.assert_allclose(modified_kz(kz, dz, order), sp.kz_modified(kz, dz, order), rtol=1e-12, atol=1e-12)
+    want = st.resonance_kz(1958.0, order, dz, 0.0)
+    got = resonance_kz(1958.0, order, dz)
+    if np.isnan(want):
+        assert np.isnan(got)
+    else:
+        assert got == pytest.approx(want, rel=1e-6)
+
+
+def test_resonance_table_of_the_survey():
+    # k_z dz at the resonance for gamma = 2000 (on axis): 0.3079 (p = 8),
+    # 0.8188 (16), 1.3764 (32), 1.8511 (64)
+    from paper_1611_05712_amd.accuracy import resonance_kz
+    for p, want in ((8, 0.3079), (16, 0.8188), (32, 1.3764), (64, 1.8511)):
+        assert resonance_kz(2000.0, p, 1.0) == pytest.approx(want, abs=2e-4)

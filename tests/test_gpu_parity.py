@@ -425,3 +425,39 @@ def test_full_cycle_with_self_field_beam_in_plasma():
     for m in range(2):
         for which in ("E", "B"):
             assert _vector_rel(sim, o, m, which) < 1e-5, (m, which)
+
+
+@pytest.mark.parametrize("order", [0, 16])
+def test_spectral_push_with_binomial_filter_matches_oracle(order):
+    wl = _vacuum(128, 64, order)
+    wl.filter = 1
+    F = _random_fields(wl, seed=40 + order)
+    sim = _sim(wl)
+    for m in range(2):
+        for c in range(11):
+            sim.set_field(m, c, F[m, c])
+    sim.spectral_push()
+    o = OracleSim(wl)
+    o.set_fields(F[:, 0:3], F[:, 3:6])
+    o.J = F[:, 6:9].copy()
+    o.rho_old = F[:, 9].copy()
+    o.rho_new = F[:, 10].copy()
+    o.spectral_push()
+    worst = 0.0
+    for m in range(2):
+        for c, name in enumerate(COMPS):
+            want = (o.E if c < 3 else o.B)[m, c % 3]
+            worst = max(worst, _rel(sim.get_field(m, name), want))
+    assert worst < FIELD_TOL, worst
+
+
+def test_full_cycle_with_binomial_filter():
+    wl = preset("small")
+    wl.filter = 1
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.step(2)
+    o.step(2)
+    for m in range(2):
+        for which in ("E", "B"):
+            assert _vector_rel(sim, o, m, which) < 1e-5, (m, which)

@@ -426,3 +426,17 @@ def test_resonance_closed_form_order4():
     # the resonance moves to larger k_z as the order grows (Fig. 2/3 discussion)
     ks = [st.resonance_kz(3.0, p, 1.0) for p in (4, 8, 16, 32, 64)]
     assert all(a < b for a, b in zip(ks, ks[1:]))
+
+
+def test_binomial_filter_is_the_121_stencil():
+    # the spectral factor cos^2(k_z dz / 2) is exactly the periodic
+    # (1/4, 1/2, 1/4) average along z, and vanishes at the Nyquist wavenumber
+    nz, dz = 32, 0.05
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal(nz) + 1j * rng.standard_normal(nz)
+    kz = sp.kz_grid(nz, dz)
+    f = sp.binomial_filter(kz, dz, np.array([0.0]), 0.1)[0]
+    got = np.fft.ifft(np.fft.fft(g) * f)
+    want = 0.25 * np.roll(g, 1) + 0.5 * g + 0.25 * np.roll(g, -1)
+    np.testing.assert_allclose(got, want, atol=1e-14)
+    assert abs(f[nz // 2]) < 1e-30 and f[0] == 1.0

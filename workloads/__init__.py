@@ -90,6 +90,7 @@ class Workload:
     steps: int
     species: List[Species]
     n0_m3: float = 1e23
+    filter: int = 0          # binomial J / rho smoothing passes before the field update (0 or 1)
 
     @property
     def n_mobile(self) -> int:
@@ -223,19 +224,20 @@ PAPER_STEPS = 175_000       # 35 mm of propagation at dt = dz / c
 
 def paper_accuracy(order: int, witness_offset: float, seed: int = 0, n_drive: int = 1_000_000,
                    n_witness: int = 200_000, nz: int = 1024, nr: int = 320,
-                   self_field: bool = True) -> Workload:
+                   self_field: bool = True, witness_mev: float = 25.0, filter: int = 0) -> Workload:
     """Cold 1 GeV, 180 pC drive (8.4 um rms length, 5 um rms width) and cold
     25 MeV, 50 pC witness (2 um, 1 um) in a 1e17 cm^-3 plasma, 2x2x4 particles
     per cell, two modes, dt = dz/c, moving window.  The box is the paper's
     900 x 300 cells rounded up to 1024 x 320 (the FFT length and the radial tile
     size); the drive sits at 3/4 of the box, the witness `witness_offset`
     (1/k_p) behind it.  Both beams start with their own space-charge field
-    (`self_field`)."""
+    (`self_field`).  `witness_mev` is the witness kinetic energy (25 MeV in
+    the paper)."""
     zmin = 0.0
     ele, ion = _plasma_species(nz, nr, PAPER_DZ, PAPER_DR, zmin)
     zd = zmin + 0.75 * nz * PAPER_DZ
     g_drive = 1.0 + 1000.0 / M_E_MEV
-    g_wit = 1.0 + 25.0 / M_E_MEV
+    g_wit = 1.0 + witness_mev / M_E_MEV
     drive = _bunch_species("drive", n_drive, 180e-12, g_drive, 5.0 * UM, 8.4 * UM, zd, seed, True,
                            self_field)
     species = [ele, ion, drive]
@@ -243,7 +245,7 @@ def paper_accuracy(order: int, witness_offset: float, seed: int = 0, n_drive: in
         species.append(_bunch_species("witness", n_witness, 50e-12, g_wit, 1.0 * UM, 2.0 * UM,
                                       zd - witness_offset, seed + 1, True, self_field))
     return Workload(f"paper_p{order}", nz, nr, 2, order, PAPER_DZ, PAPER_DR, PAPER_DZ, zmin, True,
-                    KPERP_JM_ZEROS, PAPER_STEPS, species)
+                    KPERP_JM_ZEROS, PAPER_STEPS, species, filter=filter)
 
 
 # ---------------------------------------------------------------------------
