@@ -135,29 +135,33 @@ def errors(run_f, run_inf, ez_f=None, ez_inf=None, mark=-1):
     return out
 
 
-def report(outdir: str):
+def report(outdir: str, reference: int = 0):
+    """Errors of every other order against the `reference` order's run
+    (0 = infinite order, the paper's reference)."""
     runs = {}
     for f in os.listdir(outdir):
         if f.startswith("run_p") and f.endswith(".json"):
             r = json.load(open(os.path.join(outdir, f)))
             runs[r["order"]] = r
-    if 0 not in runs:
-        raise SystemExit("no infinite-order run (p = 0) in " + outdir)
+    if reference not in runs:
+        raise SystemExit(f"no run of the reference order p = {reference} in " + outdir)
     ez = {p: np.load(os.path.join(outdir, f"ez_p{p}.npy")) for p in runs
           if os.path.exists(os.path.join(outdir, f"ez_p{p}.npy"))}
     from workloads import PAPER_DZ, M_E_MEV
     g_drive = 1.0 + 1000.0 / M_E_MEV
     rows = []
-    for p in sorted(k for k in runs if k):
-        e = errors(runs[p], runs[0], ez.get(p), ez.get(0))
-        if p in ez and 0 in ez:
-            kpk, ratio = ez_excess_peak(ez[p], ez[0], PAPER_DZ, ez[p].shape[0] // 8)
+    for p in sorted(k for k in runs if k != reference):
+        e = errors(runs[p], runs[reference], ez.get(p), ez.get(reference))
+        if p and p in ez and reference in ez:
+            kpk, ratio = ez_excess_peak(ez[p], ez[reference], PAPER_DZ, ez[p].shape[0] // 8)
             e["ez_excess_kz_dz"] = kpk * PAPER_DZ
             e["ez_excess_ratio"] = ratio
             e["resonance_kz_dz_drive"] = resonance_kz(g_drive, p, PAPER_DZ) * PAPER_DZ
         rows.append(e)
-    return {"rows": rows, "inf": {k: runs[0]["marks"][-1]["witness"][k]
-                                  for k in ("mean_gamma", "mean_slice_sigma_gamma", "eps_nx", "n")},
+    return {"reference": reference, "rows": rows,
+            "final": {p: {k: r["marks"][-1][b][k] for b in ("witness",) for k in
+                          ("mean_gamma", "mean_slice_sigma_gamma", "eps_nx", "n")} | {
+                          "drive_eps_nx": r["marks"][-1]["drive"]["eps_nx"]} for p, r in runs.items()},
             "ms_per_step": {p: r["ms_per_step"] for p, r in runs.items()}}
 
 
@@ -172,9 +176,10 @@ def main(argv=None):
     ap.add_argument("--filter", type=int, default=0, choices=[0, 1],
                     help="binomial J/rho filter passes (pic_config.filter)")
     ap.add_argument("--report", metavar="DIR")
+    ap.add_argument("--reference", type=int, default=0, help="reference order of the report (0 = infinite)")
     a = ap.parse_args(argv)
     if a.report:
-        print(json.dumps(report(a.report), indent=1))
+        print(json.dumps(report(a.report, a.reference), indent=1))
         return
     for p in a.orders:
         run_order(p, a.steps, a.out, a.marks, log=lambda m: print(m, file=sys.stderr, flush=True),
