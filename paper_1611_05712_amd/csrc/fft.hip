@@ -3,8 +3,8 @@
 // One row of nz complex values lives in LDS (ping-pong buffers); the first
 // radix pass reads straight from global memory and the last one writes
 // straight to global memory, both coalesced (consecutive butterflies touch
-// consecutive addresses).  Radix-4 passes, plus one radix-2 pass when log2(nz)
-// is odd.  Twiddles come from an FP64-built float32 table of
+// consecutive addresses).  Radix-8 passes, plus one radix-2 or radix-4 pass
+// for log2(nz) mod 3 (2048 points: four passes).  Twiddles come from an FP64-built float32 table of
 // exp(-2 pi i t / nz).
 //
 // The inverse transform can fuse the moving-window shift: output sample j is
@@ -16,8 +16,33 @@
 namespace pic {
 
 template <int R, bool INV>
+__device__ __forceinline__ void dft_small(float2* v);
+
+// radix 8: two radix-4 DFTs of the even and odd samples, odd ones rotated by
+// W8^k = exp(-/+ i pi k / 4), then one radix-2 stage
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* v) {
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft_small<4, INV>(e);
+  dft_small<4, INV>(o);
+  const float h = 0.70710678118654752f;
+  const float sg = INV ? 1.f : -1.f;
+  o[1] = cmul(o[1], make_float2(h, sg * h));
+  o[2] = cmuli(cscale(o[2], sg));
+  o[3] = cmul(o[3], make_float2(-h, sg * h));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = cadd(e[k], o[k]);
+    v[k + 4] = csub(e[k], o[k]);
+  }
+}
+
+template <int R, bool INV>
 __device__ __forceinline__ void dft_small(float2* v) {
-  if constexpr (R == 2) {
+  if constexpr (R == 8) {
+    dft8<INV>(v);
+  } else if constexpr (R == 2) {
     float2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
@@ -108,37 +133,42 @@ __global__ __launch_bounds__(256) void k_fft(const float2* __restrict__ in, floa
   o.scale = INV ? 1.f / (float)N : 1.f;
   o.tail = tail;
   o.row = row;
-  // pass plan: optional radix-2 first, then radix-4 passes
-  const bool odd = logN & 1;
-  const int n4 = logN >> 1;
-  int npass = n4 + (odd ? 1 : 0);
+  // pass plan: one radix-2 or radix-4 pass for log2(N) mod 3, then radix-8 passes
+  const int rem = logN % 3;
+  const int n8 = logN / 3;
+  const int npass = n8 + (rem ? 1 : 0);
   int Ns = 1;
   int pass = 0;
   const float2* src = gin;
   float2* cur = b0;
   float2* other = b1;
-  if (odd) {
-    bool last = (pass == npass - 1);
+  if (rem) {
+    const bool last = (pass == npass - 1);
     if (active) {
-      if (last) fft_pass<2, INV, true>(src, gout, tw, N, Ns, t, tpr, o);
-      else fft_pass<2, INV, false>(src, cur, tw, N, Ns, t, tpr, o);
+      if (rem == 1) {
+        if (last) fft_pass<2, INV, true>(src, gout, tw, N, Ns, t, tpr, o);
+        else fft_pass<2, INV, false>(src, cur, tw, N, Ns, t, tpr, o);
+      } else {
+        if (last) fft_pass<4, INV, true>(src, gout, tw, N, Ns, t, tpr, o);
+        else fft_pass<4, INV, false>(src, cur, tw, N, Ns, t, tpr, o);
+      }
     }
     __syncthreads();
-    Ns *= 2;
+    Ns *= (rem == 1) ? 2 : 4;
     ++pass;
     src = cur;
     float2* tmp = cur;
     cur = other;
     other = tmp;
   }
-  for (int q = 0; q < n4; ++q) {
-    bool last = (pass == npass - 1);
+  for (int q = 0; q < n8; ++q) {
+    const bool last = (pass == npass - 1);
     if (active) {
-      if (last) fft_pass<4, INV, true>(src, gout, tw, N, Ns, t, tpr, o);
-      else fft_pass<4, INV, false>(src, cur, tw, N, Ns, t, tpr, o);
+      if (last) fft_pass<8, INV, true>(src, gout, tw, N, Ns, t, tpr, o);
+      else fft_pass<8, INV, false>(src, cur, tw, N, Ns, t, tpr, o);
     }
     __syncthreads();
-    Ns *= 4;
+    Ns *= 8;
     ++pass;
     src = cur;
     float2* tmp = cur;
