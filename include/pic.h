@@ -104,9 +104,9 @@ typedef struct {
   int32_t hankel_prec;        /* pic_hankel_prec */
   int32_t current_correction; /* 1 (default); 0 disables the spectral correction */
   int32_t filter;             /* binomial smoothing of J and rho before the field update:
-                                 0 = none (default); 1 = one 1-2-1 pass along z and along r,
-                                 applied in spectral space as the factor
-                                 cos^2(k_z dz / 2) cos^2(k_perp dr / 2) (zero at the z Nyquist
+                                 0 = none (default); n = 1..4 passes of the 1-2-1 average along
+                                 z and along r, applied in spectral space as the factor
+                                 [cos^2(k_z dz / 2) cos^2(k_perp dr / 2)]^n (zero at the z Nyquist
                                  wavenumber, where a beam at dt = dz / c drives the numerical
                                  Cherenkov instability of the infinite-order solver) */
 } pic_config;

@@ -175,7 +175,7 @@ class OracleSim:
             r0 = hk.forward(self.rho_old[m], m)
             r1 = hk.forward(self.rho_new[m], m)
             if self.filter:
-                f = sp.binomial_filter(self.kz, self.dz, hk.k, self.dr)
+                f = sp.binomial_filter(self.kz, self.dz, hk.k, self.dr, self.filter)
                 Jh = tuple(f * j for j in Jh)
                 r0, r1 = f * r0, f * r1
             if self.correct:

@@ -193,11 +193,12 @@ def psatd_push(E, B, J, rho_old, rho_new, dt, kp, kzm):
     return En, Bn
 
 
-def binomial_filter(kz, dz, kperp, dr):
-    """One (1/4, 1/2, 1/4) smoothing pass along z and along r in spectral form,
-    cos^2(k_z dz/2) cos^2(k_perp dr/2), shape [k_perp, k_z] (an option of the
-    field update, not part of the paper's scheme)."""
-    return np.cos(0.5 * np.asarray(kperp)[:, None] * dr) ** 2 * np.cos(0.5 * np.asarray(kz)[None, :] * dz) ** 2
+def binomial_filter(kz, dz, kperp, dr, passes=1):
+    """`passes` (1/4, 1/2, 1/4) smoothing passes along z and along r in spectral
+    form, [cos^2(k_z dz/2) cos^2(k_perp dr/2)]^passes, shape [k_perp, k_z] (an
+    option of the field update, not part of the paper's scheme)."""
+    f = np.cos(0.5 * np.asarray(kperp)[:, None] * dr) ** 2 * np.cos(0.5 * np.asarray(kz)[None, :] * dz) ** 2
+    return f ** passes
 
 
 def hankel_orders(m: int):

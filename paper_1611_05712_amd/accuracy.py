@@ -173,7 +173,7 @@ def main(argv=None):
     ap.add_argument("--out", default="accuracy_runs")
     ap.add_argument("--witness-mev", type=float, default=25.0,
                     help="witness kinetic energy (the paper's set-up: 25 MeV)")
-    ap.add_argument("--filter", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--filter", type=int, default=0, choices=[0, 1, 2, 3, 4],
                     help="binomial J/rho filter passes (pic_config.filter)")
     ap.add_argument("--report", metavar="DIR")
     ap.add_argument("--reference", type=int, default=0, help="reference order of the report (0 = infinite)")

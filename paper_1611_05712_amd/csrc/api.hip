@@ -159,7 +159,7 @@ int validate(const pic_config* c, const pic_species* s, int ns) {
   if (c->moving_window && fabs(c->dt - c->dz) > 1e-12 * c->dz) return PIC_EINVAL;
   if (c->kperp_grid < 0 || c->kperp_grid > 2) return PIC_EINVAL;
   if (c->hankel_prec < 0 || c->hankel_prec > 2) return PIC_EINVAL;
-  if (c->filter < 0 || c->filter > 1) return PIC_EINVAL;
+  if (c->filter < 0 || c->filter > 4) return PIC_EINVAL;
   if (ns < 0 || ns > kMaxSpecies || (ns > 0 && !s)) return PIC_EINVAL;
   for (int i = 0; i < ns; ++i) {
     const pic_species& p = s[i];

@@ -80,9 +80,12 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
     }
     float2 r0 = *f[9], r1 = *f[10];
     if (filter) {
-      // one binomial (1/4, 1/2, 1/4) pass along z and along r, in spectral form
+      // `filter` binomial (1/4, 1/2, 1/4) passes along z and along r, in spectral form
       const double cz = cos(0.5 * kz_grid[iz] * dz), cr = cos(0.5 * kpd * dr);
-      const float fs = (float)(cz * cz * cr * cr);
+      const double f1 = cz * cz * cr * cr;
+      double fp = f1;
+      for (int q = 1; q < filter; ++q) fp *= f1;
+      const float fs = (float)fp;
 #pragma unroll
       for (int c = 0; c < 3; ++c) J[c] = cscale(J[c], fs);
       r0 = cscale(r0, fs);

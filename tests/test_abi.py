@@ -62,7 +62,7 @@ def test_workspace_bytes_valid_and_scaling(lib):
 @pytest.mark.parametrize("bad", [
     dict(nz=100), dict(nz=32), dict(nz=8192), dict(nr=48), dict(nr=16), dict(n_modes=0),
     dict(n_modes=5), dict(order=3), dict(order=-2), dict(dz=0.0), dict(dt=-1.0),
-    dict(dt=0.05), dict(kperp_grid=7), dict(hankel_prec=3), dict(dr=float("nan")), dict(filter=2),
+    dict(dt=0.05), dict(kperp_grid=7), dict(hankel_prec=3), dict(dr=float("nan")), dict(filter=5),
 ])
 def test_invalid_configs_rejected(lib, bad):
     rc, _ = _bytes(lib, _cfg(**bad))

@@ -52,12 +52,12 @@ def _gauss_residual(sim, m):
     kp = hk.k[:, None]
     rho = hk.forward(sim.rho_new[m], m)
     if sim.filter:
-        rho = rho * sp.binomial_filter(sim.kz, sim.dz, hk.k, sim.dr)
+        rho = rho * sp.binomial_filter(sim.kz, sim.dz, hk.k, sim.dr, sim.filter)
     return sp.div(tuple(sim.Eh[m]), kp, sim.kzm) - rho, \
         np.cos(np.sqrt(kp ** 2 + sim.kzm ** 2) * sim.dt)
 
 
-@pytest.mark.parametrize("correct,filt", [(True, 0), (False, 0), (True, 1)])
+@pytest.mark.parametrize("correct,filt", [(True, 0), (False, 0), (True, 1), (True, 2)])
 def test_gauss_law_error_decays_by_C_in_full_cycle(correct, filt):
     # (with the binomial filter the rule holds for the filtered densities)
     wl = preset("tiny")

@@ -440,3 +440,14 @@ def test_binomial_filter_is_the_121_stencil():
     want = 0.25 * np.roll(g, 1) + 0.5 * g + 0.25 * np.roll(g, -1)
     np.testing.assert_allclose(got, want, atol=1e-14)
     assert abs(f[nz // 2]) < 1e-30 and f[0] == 1.0
+
+
+def test_two_binomial_passes_are_the_14641_stencil():
+    nz, dz = 32, 0.05
+    rng = np.random.default_rng(2)
+    g = rng.standard_normal(nz) + 1j * rng.standard_normal(nz)
+    kz = sp.kz_grid(nz, dz)
+    f = sp.binomial_filter(kz, dz, np.array([0.0]), 0.1, passes=2)[0]
+    got = np.fft.ifft(np.fft.fft(g) * f)
+    want = (np.roll(g, 2) + 4 * np.roll(g, 1) + 6 * g + 4 * np.roll(g, -1) + np.roll(g, -2)) / 16
+    np.testing.assert_allclose(got, want, atol=1e-14)
