@@ -135,10 +135,11 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
 }
 
 // tailhat[c][m][k] = sum_r F_nu[k][r] tail[c][m][r]  (F stored transposed: ft[r][k]).
-// Workgroup (row, 64-wide k block): 4 waves split the r sum, LDS reduction.
-__global__ __launch_bounds__(256) void k_tail_transform(const float2* __restrict__ tail, float2* __restrict__ tailhat,
-                                                        const float* const* __restrict__ ft_of_row, int nr) {
-  __shared__ float2 part[4][64];
+// Workgroup (row, 64-wide k block): 16 waves split the r sum (several loads in
+// flight per wave), LDS reduction in a fixed order.
+__global__ __launch_bounds__(1024) void k_tail_transform(const float2* __restrict__ tail, float2* __restrict__ tailhat,
+                                                         const float* const* __restrict__ ft_of_row, int nr) {
+  __shared__ float2 part[16][64];
   const int row = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + lane;
@@ -146,9 +147,10 @@ __global__ __launch_bounds__(256) void k_tail_transform(const float2* __restrict
   const float2* t = tail + (size_t)row * nr;
   float sx = 0.f, sy = 0.f;
   if (k < nr) {
-    for (int r = wave; r < nr; r += 4) {
-      float a = ft[(size_t)r * nr + k];
-      float2 v = t[r];
+#pragma unroll 8
+    for (int r = wave; r < nr; r += 16) {
+      const float a = ft[(size_t)r * nr + k];
+      const float2 v = t[r];
       sx += a * v.x;
       sy += a * v.y;
     }
@@ -156,9 +158,9 @@ __global__ __launch_bounds__(256) void k_tail_transform(const float2* __restrict
   part[wave][lane] = make_float2(sx, sy);
   __syncthreads();
   if (wave == 0 && k < nr) {
-    float2 s = part[0][lane];
-    for (int w = 1; w < 4; ++w) s = cadd(s, part[w][lane]);
-    tailhat[(size_t)row * nr + k] = s;
+    float2 acc = part[0][lane];
+    for (int w = 1; w < 16; ++w) acc = cadd(acc, part[w][lane]);
+    tailhat[(size_t)row * nr + k] = acc;
   }
 }
 
@@ -216,7 +218,7 @@ void launch_psatd(float2* spec, const double* kperp, const double* kzm, const fl
 
 void launch_tail_transform(const float2* tail, float2* tailhat, const float* const* ft_of_row, int nr, int nrows,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_tail_transform, dim3((nr + 63) / 64, nrows), dim3(256), 0, s, tail, tailhat, ft_of_row, nr);
+  hipLaunchKernelGGL(k_tail_transform, dim3((nr + 63) / 64, nrows), dim3(1024), 0, s, tail, tailhat, ft_of_row, nr);
 }
 
 }  // namespace pic
