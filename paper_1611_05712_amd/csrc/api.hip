@@ -33,11 +33,6 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, s, (uint32_t*)p, nw);
 }
 
-__global__ void k_window_advance(DevState* st, double zmin0, double dz) {
-  st->n_shift += 1;
-  st->zmin = zmin0 + (double)st->n_shift * dz;
-}
-
 __global__ void k_state_init(DevState* st, double zmin, int n_part) {
   st->zmin = zmin;
   st->n_shift = 0;
@@ -223,7 +218,7 @@ size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
   int* offset = cv.take<int>(ncells + 2);
   int* cursor = cv.take<int>(ncells + 2);
   int* bsum = cv.take<int>(scan_scratch_ints(ncells + 1));
-  int* dep_nchunk = cv.take<int>(dep.ntiles);
+  int* dep_nchunk = cv.take<int>(2 * (size_t)dep.ntiles + 1);   // chunk counts, then the dense-tile list
   int* dep_start = cv.take<int>(dep.ntiles + 1);
   float2* dep_partial = cv.take<float2>((size_t)dep.max_items * dep.acc_floats2);
   float2* real = cv.take<float2>(kNumComp * M * plane);
@@ -738,8 +733,7 @@ int pic_spectral_push(pic_ctx* x) {
   }
   if (mw) {
     Phase ph(x, PIC_T_WINDOW);
-    launch_tail_transform(x->tail, x->tailhat, x->ptr_tab + x->pt_tail, nr, 6 * M, s);
-    hipLaunchKernelGGL(k_window_advance, dim3(1), dim3(1), 0, s, x->st, x->cfg.z_min, x->cfg.dz);
+    launch_tail_transform(x->tail, x->tailhat, x->ptr_tab + x->pt_tail, nr, 6 * M, x->st, x->cfg.z_min, x->cfg.dz, s);
     if (x->inj.total > 0) launch_inject(x->parts[x->cur], x->st, x->g, x->inj, (int)x->cap, s);
     x->spec_pending = true;
     x->n_shift += 1;

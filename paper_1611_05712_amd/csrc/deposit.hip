@@ -71,30 +71,54 @@ __global__ __launch_bounds__(256) void k_tile_totals(const int* __restrict__ off
   if (lane == 0) nchunk[t] = s > tg.tile_max ? (s + tg.chunk - 1) / tg.chunk : 1;
 }
 
-// exclusive scan of chunk counts: chunk_start[0..ntiles], chunk_start[ntiles] = work items
+// Exclusive scans over the tiles (wave scans, then the wave totals): the
+// chunk counts give chunk_start[0..ntiles] (chunk_start[ntiles] = work
+// items), the tiles cut into more than one chunk are listed in ascending order
+// in dense[0..ndense), with ndense stored in dense[ntiles].
 __global__ __launch_bounds__(1024) void k_tile_plan(const int* __restrict__ nchunk, int ntiles,
-                                                   int* __restrict__ chunk_start) {
-  __shared__ int sh[1024];
-  __shared__ int carry;
-  if (threadIdx.x == 0) carry = 0;
+                                                   int* __restrict__ chunk_start, int* __restrict__ dense) {
+  __shared__ int wsum[2][16];
+  __shared__ int carry[2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry[0] = carry[1] = 0;
   __syncthreads();
   for (int b0 = 0; b0 < ntiles; b0 += 1024) {
-    int i = b0 + threadIdx.x;
-    int v = i < ntiles ? nchunk[i] : 0;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      int u = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += u;
-      __syncthreads();
+    const int i = b0 + threadIdx.x;
+    const int v = i < ntiles ? nchunk[i] : 0;
+    const int f = v > 1 ? 1 : 0;
+    int a = v, d = f;   // inclusive scans within the wave
+    for (int off = 1; off < 64; off <<= 1) {
+      const int ua = __shfl_up(a, off, 64), ud = __shfl_up(d, off, 64);
+      if (lane >= off) {
+        a += ua;
+        d += ud;
+      }
     }
-    if (i < ntiles) chunk_start[i] = carry + sh[threadIdx.x] - v;
+    if (lane == 63) {
+      wsum[0][wave] = a;
+      wsum[1][wave] = d;
+    }
     __syncthreads();
-    if (threadIdx.x == 1023) carry += sh[1023];
+    int pa = carry[0], pd = carry[1];
+    for (int w = 0; w < wave; ++w) {
+      pa += wsum[0][w];
+      pd += wsum[1][w];
+    }
+    if (i < ntiles) {
+      chunk_start[i] = pa + a - v;
+      if (f) dense[pd + d - 1] = i;
+    }
+    __syncthreads();   // carry and wsum are read by every thread before they change
+    if (threadIdx.x == 1023) {
+      carry[0] = pa + a;
+      carry[1] = pd + d;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) chunk_start[ntiles] = carry;
+  if (threadIdx.x == 0) {
+    chunk_start[ntiles] = carry[0];
+    dense[ntiles] = carry[1];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -489,30 +513,35 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
   for (int e = tid; e < nacc; e += blockDim.x) dst[e] = (float)lds[e];
 }
 
-// Chunks of a dense tile: their blocks are summed into the tile's first slot
-// (grid: tiles x element blocks, one element per thread).
+// Chunks of a dense tile: their blocks are summed into the tile's first slot.
+// Work items are (dense tile, 256-element block) pairs taken from the dense
+// list in a grid-stride loop, so a launch of fixed size covers any number of
+// dense tiles and the sparse tiles cost nothing.
 template <int TR, int H, int M>
-__global__ __launch_bounds__(256) void k_chunk_reduce(const int* __restrict__ nchunk,
+__global__ __launch_bounds__(256) void k_chunk_reduce(const int* __restrict__ nchunk, const int* __restrict__ dense,
                                                       const int* __restrict__ chunk_start, float* __restrict__ scratch,
                                                       int ntiles) {
   using B = Blk<TR, H>;
   constexpr int nacc = Vals<M>::N * B::NODES;
-  const int t = blockIdx.x;
-  const int e = blockIdx.y * 256 + threadIdx.x;
-  if (t >= ntiles || e >= nacc) return;
-  const int nch = nchunk[t];
-  if (nch <= 1) return;
-  float* base = scratch + (size_t)chunk_start[t] * nacc + e;
-  float a0 = base[0], a1 = 0.f, a2 = 0.f, a3 = 0.f;
-  int c = 1;
-  for (; c + 3 < nch; c += 4) {
-    a0 += base[(size_t)c * nacc];
-    a1 += base[(size_t)(c + 1) * nacc];
-    a2 += base[(size_t)(c + 2) * nacc];
-    a3 += base[(size_t)(c + 3) * nacc];
+  constexpr int neb = (nacc + 255) / 256;
+  const int items = dense[ntiles] * neb;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int t = dense[item / neb];
+    const int e = (item % neb) * 256 + threadIdx.x;
+    if (e >= nacc) continue;
+    const int nch = nchunk[t];
+    float* base = scratch + (size_t)chunk_start[t] * nacc + e;
+    float a0 = base[0], a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    int c = 1;
+    for (; c + 3 < nch; c += 4) {
+      a0 += base[(size_t)c * nacc];
+      a1 += base[(size_t)(c + 1) * nacc];
+      a2 += base[(size_t)(c + 2) * nacc];
+      a3 += base[(size_t)(c + 3) * nacc];
+    }
+    for (; c < nch; ++c) a0 += base[(size_t)c * nacc];
+    base[0] = (a0 + a1) + (a2 + a3);
   }
-  for (; c < nch; ++c) a0 += base[(size_t)c * nacc];
-  base[0] = (a0 + a1) + (a2 + a3);
 }
 
 // Node-parallel sum of the tile blocks covering the node, then: J-,0 =
@@ -610,7 +639,7 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
   const size_t lds = (size_t)Vals<M>::N * Blk<TR, H>::NODES * sizeof(double);
   if (stages & kDepPlan) {
     hipLaunchKernelGGL((k_tile_totals<TR>), dim3((d.ntiles + 3) / 4), dim3(256), 0, s, offset, g, tg, nchunk);
-    hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(1024), 0, s, nchunk, d.ntiles, chunk_start);
+    hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(1024), 0, s, nchunk, d.ntiles, chunk_start, nchunk + d.ntiles);
   }
   if (stages & kDepTiles) {
     static bool attr_set = false;   // dynamic LDS above the default limit
@@ -625,8 +654,9 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
   }
   if (stages & kDepCombine) {
     constexpr int nacc = Vals<M>::N * Blk<TR, H>::NODES;
-    hipLaunchKernelGGL((k_chunk_reduce<TR, H, M>), dim3(d.ntiles, (nacc + 255) / 256), dim3(256), 0, s, nchunk,
-                       chunk_start, (float*)scratch, d.ntiles);
+    const int items = d.ntiles * ((nacc + 255) / 256);
+    hipLaunchKernelGGL((k_chunk_reduce<TR, H, M>), dim3(items < 1024 ? items : 1024), dim3(256), 0, s, nchunk,
+                       nchunk + d.ntiles, chunk_start, (float*)scratch, d.ntiles);
     const int64_t nodes = (int64_t)g.nr * g.nz;
     hipLaunchKernelGGL((k_deposit_combine<TR, H, M>), dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, s,
                        chunk_start, (const float*)scratch, real, bg, g, tg);

@@ -57,7 +57,9 @@ struct DepositShape {
   int tile_max;         // tiles above this many particles are chunked (3 x chunk)
 };
 DepositShape deposit_shape(int nz, int nr, int nmodes, int halo, int64_t cap);
-// stages of the deposit: work-list planning, tile accumulation, node combine
+// stages of the deposit: work-list planning, tile accumulation, node combine.
+// nchunk holds 2 ntiles + 1 ints: chunks per tile, then the list of tiles with
+// more than one chunk and its length; chunk_start holds ntiles + 1.
 constexpr int kDepPlan = 1, kDepTiles = 2, kDepCombine = 4, kDepAll = 7;
 void launch_deposit(const Parts& p, const int* offset, const DepositShape& d, int* nchunk, int* chunk_start,
                     float2* scratch, float2* real, const float2* bg, const Grid& g, DevState* st, int stages,
@@ -77,8 +79,9 @@ void launch_psatd(float2* spec, const double* kperp, const double* kzm, const fl
                   double dr, int filter, hipStream_t s);
 void launch_beam_field(float2* spec, const double* kperp, const double* kzm, int nz, int nr, int M, double gamma,
                        double beta, hipStream_t s);
+// tail column transform; with st non-null also one window move of the device state
 void launch_tail_transform(const float2* tail, float2* tailhat, const float* const* ft_of_row, int nr, int nrows,
-                           hipStream_t s);
+                           DevState* st, double zmin0, double dz, hipStream_t s);
 
 // diagnostics
 int diag_partial_doubles();

@@ -61,14 +61,27 @@ __device__ __forceinline__ void wave_count(uint32_t k, int* __restrict__ count) 
 // (6M complex float32, 16-byte aligned), so a particle's four nodes are two
 // contiguous segments [(ia, j0), (ia, j0+1)] and [(ib, j0), (ib, j0+1)].
 // --------------------------------------------------------------------------
+// A workgroup packs 256 consecutive nodes: the 6M planes are read coalesced
+// into the node records in LDS, which are then written out as one contiguous
+// block with 16-byte stores (the records of a node are 6M float2, an even
+// count, and the block starts at a multiple of 256 records).
 __global__ __launch_bounds__(256) void k_pack_gather(const float2* __restrict__ real, float2* __restrict__ gf, int nr,
                                                      int nz, int M) {
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= (int64_t)nr * nz) return;
-  float2* rec = gf + node * 6 * M;
-  for (int m = 0; m < M; ++m)
+  extern __shared__ float4 rec4[];  // [256][6M] float2, 16-byte aligned
+  float2* rec = reinterpret_cast<float2*>(rec4);
+  const int64_t n = (int64_t)nr * nz;
+  const int64_t node0 = (int64_t)blockIdx.x * 256;
+  const int64_t node = node0 + threadIdx.x;
+  const int w = 6 * M;
+  if (node < n)
+    for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) rec[m * 6 + c] = real[fidx(c, m, M, nr, nz) + node];
+      for (int c = 0; c < 6; ++c) rec[threadIdx.x * w + m * 6 + c] = real[fidx(c, m, M, nr, nz) + node];
+  __syncthreads();
+  const int64_t nodes = n - node0 < 256 ? n - node0 : 256;
+  const int nq = (int)(nodes * w / 2);   // float4 count of the block
+  float4* dst = reinterpret_cast<float4*>(gf + node0 * w);
+  for (int q = threadIdx.x; q < nq; q += 256) dst[q] = rec4[q];
 }
 
 template <int M>
@@ -492,7 +505,8 @@ void launch_gather_push(const Parts& p, const float2* gf, const Grid& g, const S
   }
 }
 void launch_pack_gather(const float2* real, float2* gf, int nr, int nz, int M, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack_gather, dim3(nblk((int64_t)nr * nz, 256)), dim3(256), 0, s, real, gf, nr, nz, M);
+  hipLaunchKernelGGL(k_pack_gather, dim3(nblk((int64_t)nr * nz, 256)), dim3(256), (size_t)256 * 6 * M * sizeof(float2),
+                     s, real, gf, nr, nz, M);
 }
 void launch_keys(const Parts& p, const Grid& g, const DevState* st, uint32_t* key, int* count, int cap,
                  hipStream_t s) {

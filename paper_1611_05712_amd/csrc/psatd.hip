@@ -136,13 +136,20 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
 
 // tailhat[c][m][k] = sum_r F_nu[k][r] tail[c][m][r]  (F stored transposed: ft[r][k]).
 // Workgroup (row, 64-wide k block): 16 waves split the r sum (several loads in
-// flight per wave), LDS reduction in a fixed order.
+// flight per wave), LDS reduction in a fixed order.  The first thread of the
+// grid also advances the window state (one more move, z_min of node 0), which
+// no other part of this launch reads.
 __global__ __launch_bounds__(1024) void k_tail_transform(const float2* __restrict__ tail, float2* __restrict__ tailhat,
-                                                         const float* const* __restrict__ ft_of_row, int nr) {
+                                                         const float* const* __restrict__ ft_of_row, int nr,
+                                                         DevState* __restrict__ st, double zmin0, double dz) {
   __shared__ float2 part[16][64];
   const int row = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + lane;
+  if (st && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    st->n_shift += 1;
+    st->zmin = zmin0 + (double)st->n_shift * dz;
+  }
   const float* ft = ft_of_row[row];
   const float2* t = tail + (size_t)row * nr;
   float sx = 0.f, sy = 0.f;
@@ -217,8 +224,9 @@ void launch_psatd(float2* spec, const double* kperp, const double* kzm, const fl
 }
 
 void launch_tail_transform(const float2* tail, float2* tailhat, const float* const* ft_of_row, int nr, int nrows,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_tail_transform, dim3((nr + 63) / 64, nrows), dim3(1024), 0, s, tail, tailhat, ft_of_row, nr);
+                           DevState* st, double zmin0, double dz, hipStream_t s) {
+  hipLaunchKernelGGL(k_tail_transform, dim3((nr + 63) / 64, nrows), dim3(1024), 0, s, tail, tailhat, ft_of_row, nr,
+                     st, zmin0, dz);
 }
 
 }  // namespace pic
