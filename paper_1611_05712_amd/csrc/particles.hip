@@ -92,7 +92,8 @@ struct Gathered {
 template <int M>
 __device__ __forceinline__ void gather_node(Gathered<M>& acc, const float2* __restrict__ gf, int i, int j, int nz,
                                             float w_even, float w_odd) {
-  const float4* rec = reinterpret_cast<const float4*>(gf + ((size_t)i * nz + j) * 6 * M);
+  // 32-bit offset: nr <= 1024, nz <= 4096 and M <= 4 keep it below 2^31 float4s
+  const float4* rec = reinterpret_cast<const float4*>(gf) + (unsigned)(i * nz + j) * (unsigned)(3 * M);
 #pragma unroll
   for (int q = 0; q < 3 * M; ++q) {
     const float4 v = rec[q];
@@ -185,8 +186,8 @@ __device__ __forceinline__ uint32_t push_one(PushRec& r, const float2* __restric
   float umx = r.ux + eps * Ex, umy = r.uy + eps * Ey;
   double umz = r.uz + (double)(eps * Ez);
   float fmz = (float)umz;
-  float gm = sqrtf(1.f + umx * umx + umy * umy + fmz * fmz);
-  float tx = eps * Bx / gm, ty = eps * By / gm, tz = eps * Bz / gm;
+  const float igm = rsqrtf(1.f + umx * umx + umy * umy + fmz * fmz);   // 1 / gamma at u^-
+  float tx = eps * Bx * igm, ty = eps * By * igm, tz = eps * Bz * igm;
   float sfac = 2.f / (1.f + tx * tx + ty * ty + tz * tz);
   float sx = sfac * tx, sy = sfac * ty, sz = sfac * tz;
   float dpz = umx * ty - umy * tx;
@@ -198,7 +199,7 @@ __device__ __forceinline__ uint32_t push_one(PushRec& r, const float2* __restric
   r.ux = uqx + eps * Ex;
   r.uy = uqy + eps * Ey;
   r.uz = umz + (double)(upx * sy - upy * sx) + (double)(eps * Ez);
-  double ginv = 1.0 / sqrt(1.0 + (double)r.ux * r.ux + (double)r.uy * r.uy + r.uz * r.uz);
+  double ginv = rsqrt_f64(1.0 + (double)r.ux * r.ux + (double)r.uy * r.uy + r.uz * r.uz);
   r.x += g.dt * ((double)r.ux * ginv);
   r.y += g.dt * ((double)r.uy * ginv);
   r.z += g.dt * (r.uz * ginv);
