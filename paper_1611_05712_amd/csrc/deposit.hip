@@ -292,15 +292,26 @@ __device__ __forceinline__ void acc_flush(double* __restrict__ lds, const Acc<K>
 }
 
 // one position of one particle: flush the accumulator if the cell changed,
-// then add the node contributions
+// then add the node contributions.  The restart after a flush is folded into
+// the accumulation (old sums times 0 or 1): with no branch rewriting the
+// accumulators, the compiler keeps them in one register set instead of copying
+// them around the particle loop.
 template <int TR, int H, int K, class Set, class OffFn>
 __device__ __forceinline__ void acc_step(double* __restrict__ lds, Acc<K>& A, uint32_t key, const float (&v)[K],
                                          const ShapePos& s, const Grid& g, int J0, int C0, OffFn off) {
-  if (key != A.key) {
-    if (A.key != kInvalidKey) acc_flush<TR, H, K, Set>(lds, A, g, J0, C0, off);
-    acc_reset(A, key);
+  const bool change = key != A.key;
+  if (change && A.key != kInvalidKey) acc_flush<TR, H, K, Set>(lds, A, g, J0, C0, off);
+  const float keep = change ? 0.f : 1.f;
+  A.key = key;
+  const float fz = s.fz, fr = s.fr;
+  const float w0 = (1.f - fz) * (1.f - fr), w1 = fz * (1.f - fr), w2 = (1.f - fz) * fr, w3 = fz * fr;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    A.a[4 * k + 0] = fmaf(w0, v[k], A.a[4 * k + 0] * keep);
+    A.a[4 * k + 1] = fmaf(w1, v[k], A.a[4 * k + 1] * keep);
+    A.a[4 * k + 2] = fmaf(w2, v[k], A.a[4 * k + 2] * keep);
+    A.a[4 * k + 3] = fmaf(w3, v[k], A.a[4 * k + 3] * keep);
   }
-  acc_add(A, v, s.fz, s.fr);
 }
 
 // one particle's deposit inputs
