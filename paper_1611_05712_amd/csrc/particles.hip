@@ -92,8 +92,7 @@ struct Gathered {
 template <int M>
 __device__ __forceinline__ void gather_node(Gathered<M>& acc, const float2* __restrict__ gf, int i, int j, int nz,
                                             float w_even, float w_odd) {
-  // 32-bit offset: nr <= 1024, nz <= 4096 and M <= 4 keep it below 2^31 float4s
-  const float4* rec = reinterpret_cast<const float4*>(gf) + (unsigned)(i * nz + j) * (unsigned)(3 * M);
+  const float4* rec = reinterpret_cast<const float4*>(gf + ((size_t)i * nz + j) * 6 * M);
 #pragma unroll
   for (int q = 0; q < 3 * M; ++q) {
     const float4 v = rec[q];
