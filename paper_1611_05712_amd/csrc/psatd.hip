@@ -45,22 +45,48 @@ __device__ __forceinline__ Coef make_coef(double kp, double kz, double dt) {
   return o;
 }
 
+// One spectral cell (k_perp index, k_z index) per thread, every mode.  All
+// loads of all modes are issued before any store (the stores could alias
+// them as far as the compiler knows), and the FP64 coefficients are computed
+// while they are in flight.
+template <int M>
 __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const double* __restrict__ kperp,
                                                const double* __restrict__ kzm, const float2* __restrict__ tw,
-                                               const float2* __restrict__ tailhat, int nz, int nr, int M, double dt,
+                                               const float2* __restrict__ tailhat, int nz, int nr, double dt,
                                                int apply_shift, int correct, const double* __restrict__ kz_grid,
                                                double dz, double dr, int filter) {
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= (int64_t)nr * nz) return;
   const int ik = (int)(cell / nz);
   const int iz = (int)(cell % nz);
+  const size_t plane = (size_t)nr * nz;
+  float2 E[M][3], B[M][3], J[M][3], r0[M], r1[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      E[m][c] = spec[((size_t)c * M + m) * plane + cell];
+      B[m][c] = spec[((size_t)(3 + c) * M + m) * plane + cell];
+      J[m][c] = spec[((size_t)(6 + c) * M + m) * plane + cell];
+    }
+    r0[m] = spec[((size_t)9 * M + m) * plane + cell];
+    r1[m] = spec[((size_t)10 * M + m) * plane + cell];
+  }
+  float2 th[M][6];
+  if (apply_shift) {
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) th[m][c] = tailhat[((size_t)c * M + m) * nr + ik];
+  }
   const double kzd = kzm[iz];
   const float kz = (float)kzd;
-  const size_t plane = (size_t)nr * nz;
   float2 ph = make_float2(1.f, 0.f);
   if (apply_shift) ph = cconj(tw[iz]);   // exp(+2 pi i iz / nz)
+  const float idt = (float)(1.0 / dt);
   double kp_prev = -1.0;
   Coef co{};
+#pragma unroll
   for (int m = 0; m < M; ++m) {
     const double kpd = kperp[m * nr + ik];
     if (kpd != kp_prev) {
@@ -71,14 +97,14 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
     float2* f[kNumComp];
 #pragma unroll
     for (int c = 0; c < kNumComp; ++c) f[c] = spec + ((size_t)c * M + m) * plane + cell;
-    float2 E[3], B[3], J[3];
+    float2 Em[3], Bm[3], Jm[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      E[c] = *f[c];
-      B[c] = *f[3 + c];
-      J[c] = *f[6 + c];
+      Em[c] = E[m][c];
+      Bm[c] = B[m][c];
+      Jm[c] = J[m][c];
     }
-    float2 r0 = *f[9], r1 = *f[10];
+    float2 q0 = r0[m], q1 = r1[m];
     if (filter) {
       // `filter` binomial (1/4, 1/2, 1/4) passes along z and along r, in spectral form
       const double cz = cos(0.5 * kz_grid[iz] * dz), cr = cos(0.5 * kpd * dr);
@@ -87,47 +113,46 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
       for (int q = 1; q < filter; ++q) fp *= f1;
       const float fs = (float)fp;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) J[c] = cscale(J[c], fs);
-      r0 = cscale(r0, fs);
-      r1 = cscale(r1, fs);
+      for (int c = 0; c < 3; ++c) Jm[c] = cscale(Jm[c], fs);
+      q0 = cscale(q0, fs);
+      q1 = cscale(q1, fs);
     }
     if (apply_shift) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        E[c] = cmul(ph, csub(E[c], tailhat[((size_t)c * M + m) * nr + ik]));
-        B[c] = cmul(ph, csub(B[c], tailhat[((size_t)(3 + c) * M + m) * nr + ik]));
+        Em[c] = cmul(ph, csub(Em[c], th[m][c]));
+        Bm[c] = cmul(ph, csub(Bm[c], th[m][3 + c]));
       }
     }
-    const float idt = (float)(1.0 / dt);
     if (correct) {
-      float2 dvj = cadd(cscale(csub(J[0], J[1]), kp), cmuli(cscale(J[2], kz)));
-      float2 F = cscale(cadd(dvj, cscale(csub(r1, r0), idt)), co.ik2);
-      J[0] = cadd(J[0], cscale(F, -0.5f * kp));
-      J[1] = cadd(J[1], cscale(F, 0.5f * kp));
-      J[2] = cadd(J[2], cmuli(cscale(F, kz)));
+      float2 dvj = cadd(cscale(csub(Jm[0], Jm[1]), kp), cmuli(cscale(Jm[2], kz)));
+      float2 F = cscale(cadd(dvj, cscale(csub(q1, q0), idt)), co.ik2);
+      Jm[0] = cadd(Jm[0], cscale(F, -0.5f * kp));
+      Jm[1] = cadd(Jm[1], cscale(F, 0.5f * kp));
+      Jm[2] = cadd(Jm[2], cmuli(cscale(F, kz)));
 #pragma unroll
-      for (int c = 0; c < 3; ++c) *f[6 + c] = J[c];
+      for (int c = 0; c < 3; ++c) *f[6 + c] = Jm[c];
     }
     // curls
     float2 cB[3], cE[3], cJ[3];
     {
       const float hk = 0.5f * kp;
-      cB[0] = csub(cscale(B[0], kz), cmuli(cscale(B[2], hk)));
-      cB[1] = csub(cscale(B[1], -kz), cmuli(cscale(B[2], hk)));
-      cB[2] = cmuli(cscale(cadd(B[0], B[1]), kp));
-      cE[0] = csub(cscale(E[0], kz), cmuli(cscale(E[2], hk)));
-      cE[1] = csub(cscale(E[1], -kz), cmuli(cscale(E[2], hk)));
-      cE[2] = cmuli(cscale(cadd(E[0], E[1]), kp));
-      cJ[0] = csub(cscale(J[0], kz), cmuli(cscale(J[2], hk)));
-      cJ[1] = csub(cscale(J[1], -kz), cmuli(cscale(J[2], hk)));
-      cJ[2] = cmuli(cscale(cadd(J[0], J[1]), kp));
+      cB[0] = csub(cscale(Bm[0], kz), cmuli(cscale(Bm[2], hk)));
+      cB[1] = csub(cscale(Bm[1], -kz), cmuli(cscale(Bm[2], hk)));
+      cB[2] = cmuli(cscale(cadd(Bm[0], Bm[1]), kp));
+      cE[0] = csub(cscale(Em[0], kz), cmuli(cscale(Em[2], hk)));
+      cE[1] = csub(cscale(Em[1], -kz), cmuli(cscale(Em[2], hk)));
+      cE[2] = cmuli(cscale(cadd(Em[0], Em[1]), kp));
+      cJ[0] = csub(cscale(Jm[0], kz), cmuli(cscale(Jm[2], hk)));
+      cJ[1] = csub(cscale(Jm[1], -kz), cmuli(cscale(Jm[2], hk)));
+      cJ[2] = cmuli(cscale(cadd(Jm[0], Jm[1]), kp));
     }
-    const float2 gs = cadd(cscale(r1, co.r1), cscale(r0, co.r0));
+    const float2 gs = cadd(cscale(q1, co.r1), cscale(q0, co.r0));
     const float2 g[3] = {cscale(gs, -0.5f * kp), cscale(gs, 0.5f * kp), cmuli(cscale(gs, kz))};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float2 En = cadd(cadd(cscale(E[c], co.C), cscale(csub(cB[c], J[c]), co.Sk)), g[c]);
-      float2 Bn = cadd(csub(cscale(B[c], co.C), cscale(cE[c], co.Sk)), cscale(cJ[c], co.omc));
+      float2 En = cadd(cadd(cscale(Em[c], co.C), cscale(csub(cB[c], Jm[c]), co.Sk)), g[c]);
+      float2 Bn = cadd(csub(cscale(Bm[c], co.C), cscale(cE[c], co.Sk)), cscale(cJ[c], co.omc));
       *f[c] = En;
       *f[3 + c] = Bn;
     }
@@ -215,12 +240,24 @@ void launch_beam_field(float2* spec, const double* kperp, const double* kzm, int
                      gamma, beta);
 }
 
+template <int M>
+static void launch_psatd_m(float2* spec, const double* kperp, const double* kzm, const float2* tw,
+                           const float2* tailhat, int nz, int nr, double dt, bool apply_shift, bool correct,
+                           const double* kz_grid, double dz, double dr, int filter, hipStream_t s) {
+  const int64_t n = (int64_t)nr * nz;
+  hipLaunchKernelGGL((k_psatd<M>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spec, kperp, kzm, tw, tailhat,
+                     nz, nr, dt, apply_shift ? 1 : 0, correct ? 1 : 0, kz_grid, dz, dr, filter);
+}
+
 void launch_psatd(float2* spec, const double* kperp, const double* kzm, const float2* tw, const float2* tailhat,
                   int nz, int nr, int M, double dt, bool apply_shift, bool correct, const double* kz_grid, double dz,
                   double dr, int filter, hipStream_t s) {
-  int64_t n = (int64_t)nr * nz;
-  hipLaunchKernelGGL(k_psatd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spec, kperp, kzm, tw, tailhat, nz,
-                     nr, M, dt, apply_shift ? 1 : 0, correct ? 1 : 0, kz_grid, dz, dr, filter);
+  switch (M) {
+    case 1: launch_psatd_m<1>(spec, kperp, kzm, tw, tailhat, nz, nr, dt, apply_shift, correct, kz_grid, dz, dr, filter, s); break;
+    case 2: launch_psatd_m<2>(spec, kperp, kzm, tw, tailhat, nz, nr, dt, apply_shift, correct, kz_grid, dz, dr, filter, s); break;
+    case 3: launch_psatd_m<3>(spec, kperp, kzm, tw, tailhat, nz, nr, dt, apply_shift, correct, kz_grid, dz, dr, filter, s); break;
+    default: launch_psatd_m<4>(spec, kperp, kzm, tw, tailhat, nz, nr, dt, apply_shift, correct, kz_grid, dz, dr, filter, s); break;
+  }
 }
 
 void launch_tail_transform(const float2* tail, float2* tailhat, const float* const* ft_of_row, int nr, int nrows,
