@@ -570,10 +570,9 @@ __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__
   const int nz = g.nz, nr = g.nr;
   if (node >= (int64_t)nr * nz) return;
   const int i = (int)(node / nz), j = (int)(node % nz);
-  float acc[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.f;
-  // covering tiles: bz = j - (J0 - H) mod nz in [0, BZ); br = i - (C0 - 1 - H) in [0, BR)
+  // covering tiles (at most two along z times two along r):
+  // bz = j - (J0 - H) mod nz in [0, BZ); br = i - (C0 - 1 - H) in [0, BR)
+  int tq[4] = {0, 0, 0, 0}, toff[4] = {0, 0, 0, 0}, nt = 0;   // the centre tile always covers the node
   const int tz0 = j / kTZ;
   const int tr0 = (i + 1) / TR;
   for (int dtz = -1; dtz <= 1; ++dtz) {
@@ -591,11 +590,40 @@ __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__
       if (tr < 0 || tr >= tg.ntr) continue;
       const int br = i - (tr * TR - 1 - H);
       if (br < 0 || br >= B::BR) continue;
-      const int t = tr * tg.ntz + tz;
-      const float* q = scratch + (size_t)chunk_start[t] * nacc + br * B::BZ + bz;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] += q[v * B::NODES];
+      if (nt < 4) {
+        tq[nt] = tr * tg.ntz + tz;
+        toff[nt] = br * B::BZ + bz;
+        ++nt;
+      }
     }
+  }
+  // every load in flight at once: unused slots repeat the first tile with weight 0
+  int cs[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cs[q] = chunk_start[tq[q < nt ? q : 0]];
+  float2 bgv[M][2];
+  if (bg) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      bgv[m][0] = bg[(size_t)m * nr * nz + node];
+      bgv[m][1] = bgv[m][0];
+    }
+  }
+  float x[4][NV];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float* qp = scratch + (size_t)cs[q] * nacc + toff[q < nt ? q : 0];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[q][v] = qp[v * B::NODES];
+  }
+  float acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float wq = q < nt ? 1.f : 0.f;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = fmaf(wq, x[q][v], acc[v]);
   }
   const float inv_v = (float)(1.0 / (2.0 * M_PI * g.dr * g.dr * g.dz * (i + 0.5)));
   // slot order of the grid: J+, J-, Jz, rho^n, rho^{n+1}
@@ -616,7 +644,7 @@ __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       float2 v = cscale(out[sl][m], inv_v);
-      if (bg && sl >= 3) v = cadd(v, bg[(size_t)m * nr * nz + node]);
+      if (bg && sl >= 3) v = cadd(v, bgv[m][sl - 3]);
       real[dfidx(kCompJ + sl, m, M, nr, nz) + node] = v;
     }
 }
