@@ -159,11 +159,12 @@ __device__ __forceinline__ void gather_eb(const float2* __restrict__ gf, const S
 
 // --------------------------------------------------------------------------
 // gather + Boris push + move + new cell key + key histogram.  Each thread
-// pushes kPushPer particles, blockDim apart: all their loads are issued before
-// any of them is computed, so a wave keeps twice the memory requests in
-// flight (the kernel waits on memory, not on arithmetic).
+// pushes kPushPer particles, blockDim apart, all their loads issued before any
+// of them is computed.  Measured at 2048 x 256: one particle per thread (83
+// instead of 95 VGPRs, twice the wavefronts of half the work) beats two, three
+// or four.
 // --------------------------------------------------------------------------
-constexpr int kPushPer = 2;
+constexpr int kPushPer = 1;
 
 struct PushRec {
   double x, y, z, uz;
@@ -352,8 +353,9 @@ __global__ __launch_bounds__(256) void k_scan_apply(int* __restrict__ count, int
 
 // --------------------------------------------------------------------------
 // scatter into cell order (removed particles dropped).  Block-level
-// multisplit: the 256 keys of a block are sorted in LDS (bitonic, key then
-// original index, so the order is stable), every distinct key reserves one
+// multisplit: the 256 keys of a block are sorted (bitonic network on key then
+// original index, so the order is stable; in registers, with LDS only for the
+// stages whose partners sit in another wavefront), every distinct key reserves one
 // contiguous range of its cell with a single atomic, and thread t writes the
 // t-th particle of the sorted block, so particles bound for one cell leave
 // as one contiguous run even when the wake has scrambled the input order.
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(256) void k_scatter(Parts src, Parts dst, const uin
   const int n = st->n_part;
   uint32_t k = (i < n) ? key[i] : kInvalidKey;
   if (k >= (uint32_t)ncells) k = kInvalidKey;   // removed or past the end
-  sk[tid] = ((uint64_t)k << 32) | (uint32_t)tid;
+  uint64_t e = ((uint64_t)k << 32) | (uint32_t)tid;
   if (k != kInvalidKey) {
     PartRec r;
     r.x = src.x[i];
@@ -388,22 +390,27 @@ __global__ __launch_bounds__(256) void k_scatter(Parts src, Parts dst, const uin
     r.sp = src.sp[i];
     rec[tid] = r;
   }
-  __syncthreads();
-  // bitonic sort of 256 64-bit keys
+  // bitonic sort of the 256 keys in registers: partners within a wavefront
+  // exchange through __shfl_xor, the three stages with stride >= 64 through LDS
   for (int size = 2; size <= 256; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const int partner = tid ^ stride;
-      if (partner > tid) {
-        const bool up = (tid & size) == 0;
-        const uint64_t a = sk[tid], b = sk[partner];
-        if ((a > b) == up) {
-          sk[tid] = b;
-          sk[partner] = a;
-        }
+      uint64_t other;
+      if (stride >= 64) {
+        sk[tid] = e;
+        __syncthreads();
+        other = sk[tid ^ stride];
+        __syncthreads();
+      } else {
+        const uint32_t lo = __shfl_xor((uint32_t)e, stride, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(e >> 32), stride, 64);
+        other = ((uint64_t)hi << 32) | lo;
       }
-      __syncthreads();
+      const bool keep_min = ((tid & stride) == 0) == ((tid & size) == 0);
+      e = keep_min ? (other < e ? other : e) : (other > e ? other : e);
     }
   }
+  sk[tid] = e;
+  __syncthreads();
   const uint64_t me = sk[tid];
   const uint32_t mk = (uint32_t)(me >> 32);
   const bool first = (tid == 0) || ((uint32_t)(sk[tid - 1] >> 32) != mk);
