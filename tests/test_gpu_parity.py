@@ -131,21 +131,28 @@ def test_deposit_matches_oracle(n):
             assert np.abs(got - w).max() < 2e-6 * scale, (m, name)
 
 
-@pytest.mark.parametrize("kind", ["cluster", "axis"])
+@pytest.mark.parametrize("kind", ["cluster", "axis", "two"])
 def test_deposit_dense_clusters_match_oracle(kind):
     # tens of thousands of particles in a few cells: long same-cell runs in
     # every wavefront and tiles split over several workgroups (partial tiles
-    # combined), next to a sparse random background
+    # combined), next to a sparse random background; "two": clusters in two
+    # distant tiles, so the list of chunked tiles has several entries
     wl = _vacuum(128, 64, 16)
     rng = np.random.default_rng(17)
     n = 70000
     if kind == "cluster":
         x = rng.normal(1.0, 0.01, n)
         y = rng.normal(0.5, 0.01, n)
-    else:   # on the axis, where the ghost-node parity applies
+    elif kind == "axis":   # on the axis, where the ghost-node parity applies
         x = rng.normal(0.0, 0.01, n)
         y = rng.normal(0.0, 0.01, n)
-    z = rng.normal(3.2, 0.015, n)
+    else:
+        x = np.concatenate([rng.normal(1.0, 0.01, n // 2), rng.normal(2.4, 0.01, n - n // 2)])
+        y = np.concatenate([rng.normal(0.5, 0.01, n // 2), rng.normal(-0.3, 0.01, n - n // 2)])
+    if kind == "two":
+        z = np.concatenate([rng.normal(3.2, 0.015, n // 2), rng.normal(1.1, 0.015, n - n // 2)])
+    else:
+        z = rng.normal(3.2, 0.015, n)
     u = (0.3 * rng.standard_normal((3, n))).astype(np.float32)
     u[2] += 40.0
     bgp = random_particles(2000, wl.nz, wl.nr, wl.dz, wl.dr, wl.zmin, seed=3, u_scale=1.0)
