@@ -54,6 +54,13 @@ struct SpeciesConst {
   float qm[kMaxSpecies];   // q / m
 };
 
+// Global-address-space pointers.  A pointer read from a device-side table is
+// generic (flat): accesses through it are flat instructions, which count
+// against the LDS wait counter too, so every LDS wait also waits for them.
+// Converted to these types, the accesses are global ones.
+typedef __attribute__((address_space(1))) const float* gcfloat_p;
+typedef __attribute__((address_space(1))) float* gfloat_p;
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

@@ -38,7 +38,7 @@ struct GemmTile {
 };
 
 template <int BM, int BN>
-__device__ __forceinline__ void load_chunk(const float* __restrict__ at, const float* __restrict__ x, int n, int ncols,
+__device__ __forceinline__ void load_chunk(gcfloat_p __restrict__ at, gcfloat_p __restrict__ x, int n, int ncols,
                                            int m0, int n0, int k0, float* ra, float* rb) {
   using T = GemmTile<BM, BN>;
   const int tid = threadIdx.x;
@@ -67,7 +67,7 @@ __device__ __forceinline__ void store_chunk(float* As, float* Bs, const float* r
 }
 
 template <int BM, int BN>
-__device__ __forceinline__ void store_out(float* __restrict__ y, int ncols, int m0, int n0, const floatx16 (&acc)[BM][BN]) {
+__device__ __forceinline__ void store_out(gfloat_p __restrict__ y, int ncols, int m0, int n0, const floatx16 (&acc)[BM][BN]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < BM; ++i)
@@ -91,9 +91,9 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const float* const* __restrict
   using T = GemmTile<BM, BN>;
   __shared__ float As[2][T::A_ELEMS];
   __shared__ float Bs[2][T::B_ELEMS];
-  const float* at = AT[blockIdx.z];
-  const float* x = X[blockIdx.z];
-  float* y = Y[blockIdx.z];
+  gcfloat_p at = (gcfloat_p)AT[blockIdx.z];
+  gcfloat_p x = (gcfloat_p)X[blockIdx.z];
+  gfloat_p y = (gfloat_p)Y[blockIdx.z];
   const int m0 = blockIdx.y * T::MT, n0 = blockIdx.x * T::NT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   floatx16 acc[BM][BN];
@@ -179,9 +179,9 @@ __global__ __launch_bounds__(256) void k_gemm_split(const float* const* __restri
   using S = Split<F16>;
   __shared__ float As[2][T::A_ELEMS];
   __shared__ float Bs[2][T::B_ELEMS];
-  const float* at = AT[blockIdx.z];
-  const float* x = X[blockIdx.z];
-  float* y = Y[blockIdx.z];
+  gcfloat_p at = (gcfloat_p)AT[blockIdx.z];
+  gcfloat_p x = (gcfloat_p)X[blockIdx.z];
+  gfloat_p y = (gfloat_p)Y[blockIdx.z];
   const int m0 = blockIdx.y * T::MT, n0 = blockIdx.x * T::NT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   floatx16 acc[BM][BN], acl[BM][BN];

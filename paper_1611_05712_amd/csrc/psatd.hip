@@ -175,7 +175,7 @@ __global__ __launch_bounds__(1024) void k_tail_transform(const float2* __restric
     st->n_shift += 1;
     st->zmin = zmin0 + (double)st->n_shift * dz;
   }
-  const float* ft = ft_of_row[row];
+  gcfloat_p ft = (gcfloat_p)ft_of_row[row];
   const float2* t = tail + (size_t)row * nr;
   float sx = 0.f, sy = 0.f;
   if (k < nr) {
