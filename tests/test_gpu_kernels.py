@@ -18,7 +18,8 @@ def _gpu():
     pic.load()
 
 
-@pytest.mark.parametrize("nz,rows", [(16, 3), (64, 7), (128, 9), (256, 33), (2048, 5), (4096, 3)])
+@pytest.mark.parametrize("nz,rows", [(16, 3), (32, 5), (64, 7), (128, 9), (256, 33), (512, 6), (1024, 4),
+                                     (2048, 5), (4096, 3)])
 @pytest.mark.parametrize("inverse", [False, True])
 def test_fft_z_matches_dft(nz, rows, inverse):
     from paper_1611_05712_amd import pic

@@ -54,7 +54,7 @@ COMPS = ["E+", "E-", "Ez", "B+", "B-", "Bz"]
 
 
 @pytest.mark.parametrize("order", [0, 16, 32])
-@pytest.mark.parametrize("nz,nr", [(128, 64), (256, 96)])
+@pytest.mark.parametrize("nz,nr", [(128, 64), (256, 96), (512, 32), (1024, 32)])
 def test_spectral_push_matches_oracle(order, nz, nr):
     wl = _vacuum(nz, nr, order)
     F = _random_fields(wl, seed=order + nz)
