@@ -176,6 +176,38 @@ def test_deposit_dense_clusters_match_oracle(kind):
             assert np.abs(got - w[m]).max() < 5e-5 * scale, (m, name)
 
 
+def test_deposit_many_tiles_matches_oracle():
+    # 2048 x 256 cells: 64 x 33 = 2112 tiles, three 1024-tile blocks of the
+    # work-list scan, with a dense (chunked) cluster in the second block
+    wl = _vacuum(2048, 256, 16)
+    rng = np.random.default_rng(29)
+    n = 40000
+    x = rng.normal(9.0, 0.01, n)
+    y = rng.normal(-4.0, 0.01, n)
+    z = rng.normal(40.0, 0.015, n)
+    u = (0.3 * rng.standard_normal((3, n))).astype(np.float32)
+    u[2] += 40.0
+    bgp = random_particles(5000, wl.nz, wl.nr, wl.dz, wl.dr, wl.zmin, seed=5, u_scale=1.0)
+    p = {"x": np.concatenate([x, bgp["x"]]), "y": np.concatenate([y, bgp["y"]]),
+         "z": np.concatenate([z, bgp["z"]]), "ux": np.concatenate([u[0], bgp["ux"]]),
+         "uy": np.concatenate([u[1], bgp["uy"]]), "uz": np.concatenate([u[2], bgp["uz"]]),
+         "w": np.concatenate([np.full(n, 1e-3, np.float32), bgp["w"]])}
+    wl.species = [_species_from(p)]
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.gather_push()
+    sim.deposit()
+    o.gather_push()
+    o.deposit()
+    want = {"J+": o.J[:, 0], "J-": o.J[:, 1], "Jz": o.J[:, 2], "rho_old": o.rho_old,
+            "rho_new": o.rho_new}
+    for m in range(2):
+        for name, w in want.items():
+            got = sim.get_field(m, name)
+            scale = max(np.abs(w[m]).max(), 1e-30)
+            assert np.abs(got - w[m]).max() < 5e-5 * scale, (m, name)
+
+
 def test_deposit_outer_edge_matches_oracle():
     # particles around the outer radius R: lower node nr-1 (outer node dropped)
     # and beyond R (both nodes dropped) share the last sort-key column, which is
