@@ -542,16 +542,15 @@ __global__ __launch_bounds__(256) void k_chunk_reduce(const int* __restrict__ nc
     if (e >= nacc) continue;
     const int nch = nchunk[t];
     float* base = scratch + (size_t)chunk_start[t] * nacc + e;
-    float a0 = base[0], a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    // eight chunks in flight per batch (a beam-core tile has about twelve)
+    float a[8] = {base[0], 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int c = 1;
-    for (; c + 3 < nch; c += 4) {
-      a0 += base[(size_t)c * nacc];
-      a1 += base[(size_t)(c + 1) * nacc];
-      a2 += base[(size_t)(c + 2) * nacc];
-      a3 += base[(size_t)(c + 3) * nacc];
+    for (; c + 7 < nch; c += 8) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] += base[(size_t)(c + q) * nacc];
     }
-    for (; c < nch; ++c) a0 += base[(size_t)c * nacc];
-    base[0] = (a0 + a1) + (a2 + a3);
+    for (; c < nch; ++c) a[0] += base[(size_t)c * nacc];
+    base[0] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
 }
 
