@@ -22,9 +22,9 @@ def _sim(wl, **kw):
     return Simulation.from_workload(wl, **kw)
 
 
-def _field_rel(a, b):
+def _field_rel(a, b, modes=2):
     worst = 0.0
-    for m in range(2):
+    for m in range(modes):
         for off in (0, 3):
             ga = np.stack([a.get_field(m, COMPS[off + c]) for c in range(3)])
             gb = np.stack([b.get_field(m, COMPS[off + c]) for c in range(3)])
@@ -48,6 +48,19 @@ def test_graph_steps_match_eager(n):
     assert a.state() == b.state()
     assert a.num_particles() == b.num_particles()
     assert _field_rel(b, a) < 1e-5
+    _moments_close(b, a, "drive")
+
+
+@pytest.mark.parametrize("modes", [1, 3])
+def test_graph_steps_match_eager_other_mode_counts(modes):
+    import dataclasses
+    wl = dataclasses.replace(preset("small"), n_modes=modes)
+    a, b = _sim(wl), _sim(wl)
+    a.step(3)
+    b.step_graph(3)
+    assert a.state() == b.state()
+    assert a.num_particles() == b.num_particles()
+    assert _field_rel(b, a, modes) < 1e-5
     _moments_close(b, a, "drive")
 
 
