@@ -405,6 +405,24 @@ def test_c0_one_step_fields():
             assert _vector_rel(sim, o, m, which) < FIELD_TOL, (m, which)
 
 
+@pytest.mark.timeout(900)
+def test_c1_full_size_one_step_fields():
+    """The benchmark workload at its full size (2048 x 256, p = 32, 9.59 M
+    mobile particles, 1e6-particle drive in chunked tiles), one cycle with the
+    kernels and launch shapes the benchmark replays: each mode's E and B within
+    relative L2 1e-5 of the oracle's full step, and the same live particle
+    count.  (The oracle step takes about a minute.)"""
+    wl = preset("c1")
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.step(1)
+    o.step(1)
+    assert sim.num_particles() == sum(sp.x.size for sp in o.species if sp.mobile)
+    for m in range(2):
+        for which in ("E", "B"):
+            assert _vector_rel(sim, o, m, which) < FIELD_TOL, (m, which)
+
+
 def test_c0_fifty_steps_against_stored_oracle_run():
     """The same workload for 50 steps: drive moments after 1, 10, 25 and 50
     steps within relative 1e-4, field norms within 1e-4, live particle count
