@@ -423,6 +423,28 @@ def test_c1_full_size_one_step_fields():
             assert _vector_rel(sim, o, m, which) < FIELD_TOL, (m, which)
 
 
+@pytest.mark.timeout(300)
+def test_c1_corrected_current_continuity_after_blowout():
+    """A property at the full benchmark size, in the regime the benchmark times
+    (graph replays well into the wake): after the current correction the
+    stored spectral current obeys k_perp (J+ - J-) + i [k_z] J_z
+    + (rho^{n+1} - rho^n) / dt = 0 in every spectral cell of every mode."""
+    from oracle.spectral import div, kperp_grid, kz_grid, kz_modified
+    wl = preset("c1")
+    sim = _sim(wl)
+    sim.step_graph(300)
+    kzm = kz_modified(kz_grid(wl.nz, wl.dz), wl.dz, wl.order)[None, :]
+    for m in range(wl.n_modes):
+        kp = kperp_grid(m, wl.nr, wl.dr, wl.kperp_grid)[:, None]
+        J = [sim.get_field(m, c, spectral=True).astype(np.complex128) for c in ("J+", "J-", "Jz")]
+        r0 = sim.get_field(m, "rho_old", spectral=True).astype(np.complex128)
+        r1 = sim.get_field(m, "rho_new", spectral=True).astype(np.complex128)
+        drho = (r1 - r0) / wl.dt
+        dj = div(J, kp, kzm)
+        res = np.linalg.norm(dj + drho) / max(np.linalg.norm(drho), np.linalg.norm(dj), 1e-30)
+        assert res < 1e-4, (m, res)
+
+
 def test_c0_fifty_steps_against_stored_oracle_run():
     """The same workload for 50 steps: drive moments after 1, 10, 25 and 50
     steps within relative 1e-4, field norms within 1e-4, live particle count
