@@ -445,6 +445,60 @@ def test_c1_corrected_current_continuity_after_blowout():
         assert res < 1e-4, (m, res)
 
 
+def _c1_sample_oracle(wl, zmin, F, before, n_per_species=4000, seed=7):
+    """Oracle gather + push of a random sample of each mobile species (drawn
+    from the particles at least three cells ahead of the window tail) on the
+    c1 grid, from the given real-space E, B."""
+    rng = np.random.default_rng(seed)
+    samples = []
+    for s in wl.species:
+        if not s.mobile:
+            continue
+        b = before[s.name]
+        ok = np.nonzero(b["z"] > zmin + 3 * wl.dz)[0]
+        idx = np.sort(rng.choice(ok, size=min(n_per_species, ok.size), replace=False))
+        samples.append(Species(s.name, s.q, s.m, True, b["x"][idx], b["y"][idx], b["z"][idx],
+                               b["ux"][idx].astype(np.float32), b["uy"][idx].astype(np.float32),
+                               b["uz"][idx], b["w"][idx].astype(np.float32), diag=True))
+    ow = Workload("c1-sample", wl.nz, wl.nr, wl.n_modes, wl.order, wl.dz, wl.dr, wl.dt, zmin, False,
+                  wl.kperp_grid, 1, samples)
+    o = OracleSim(ow)
+    o.set_fields(F[:, 0:3], F[:, 3:6])
+    o.gather_push()
+    return o
+
+
+@pytest.mark.timeout(300)
+def test_c1_sampled_push_in_the_wake():
+    """Sampled outputs at the full benchmark size: after 300 graph-replayed
+    steps (fields of the wake), one gather + push on the GPU; 4000 particles of
+    each mobile species pushed by the oracle from the same particles and the
+    GPU's fields match their GPU counterparts, found by position (a push moves
+    a particle by at most one cell, the two sides agree to 1e-7)."""
+    from scipy.spatial import cKDTree
+    wl = preset("c1")
+    sim = _sim(wl)
+    sim.step_graph(300)
+    zmin, _ = sim.state()
+    F = np.zeros((wl.n_modes, 6, wl.nr, wl.nz), np.complex128)
+    for m in range(wl.n_modes):
+        for c in range(6):
+            F[m, c] = sim.get_field(m, COMPS[c])
+    names = [s.name for s in wl.species if s.mobile]
+    before = {n: sim.get_particles(n) for n in names}
+    sim.gather_push()
+    after = {n: sim.get_particles(n) for n in names}
+    o = _c1_sample_oracle(wl, zmin, F, before)
+    for name, os_ in zip(names, o.species):
+        a = after[name]
+        tree = cKDTree(np.stack([a["x"], a["y"], a["z"]], axis=1))
+        d, j = tree.query(np.stack([os_.x, os_.y, os_.z], axis=1))
+        assert d.max() < 2e-7, (name, d.max())
+        for key, ref in (("ux", os_.ux), ("uy", os_.uy), ("uz", os_.uz)):
+            np.testing.assert_allclose(a[key][j], ref, rtol=2e-5, atol=2e-5 * np.abs(ref).max(),
+                                       err_msg=f"{name} {key}")
+
+
 def test_c0_fifty_steps_against_stored_oracle_run():
     """The same workload for 50 steps: drive moments after 1, 10, 25 and 50
     steps within relative 1e-4, field norms within 1e-4, live particle count
