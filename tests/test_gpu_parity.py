@@ -499,6 +499,56 @@ def test_c1_sampled_push_in_the_wake():
                                        err_msg=f"{name} {key}")
 
 
+@pytest.mark.timeout(600)
+def test_c1_deposit_in_the_wake():
+    """The deposit at the full benchmark size in the regime the benchmark times:
+    after 300 graph-replayed steps, one gather + push and one deposit on the
+    GPU; the oracle deposits the GPU's own pushed particles (positions at n and
+    velocities from u^{n+1/2}, as the GPU defines them) with the ion lattice
+    shifted into the current window.  Every source of both modes node by node,
+    away from the three columns at each end of the window (particles that
+    crossed the tail during this push are deposited by the GPU but no longer
+    returned by it, and periodic wrap puts their rho^n at the head)."""
+    wl = preset("c1")
+    sim = _sim(wl)
+    sim.step_graph(300)
+    zmin, _ = sim.state()
+    sim.gather_push()
+    names = [s.name for s in wl.species if s.mobile]
+    after = {n: sim.get_particles(n) for n in names}
+    sim.deposit()
+    species = []
+    for s in wl.species:
+        if s.mobile:
+            a = after[s.name]
+            species.append(Species(s.name, s.q, s.m, True, a["x"], a["y"], a["z"],
+                                   a["ux"].astype(np.float32), a["uy"].astype(np.float32), a["uz"],
+                                   a["w"].astype(np.float32), diag=True))
+        else:   # uniform lattice over one window length, moved with the window
+            species.append(Species(s.name, s.q, s.m, False, s.x, s.y, s.z + zmin, s.ux, s.uy, s.uz, s.w))
+    ow = Workload("c1-deposit", wl.nz, wl.nr, wl.n_modes, wl.order, wl.dz, wl.dr, wl.dt, zmin, False,
+                  wl.kperp_grid, 1, species)
+    o = OracleSim(ow)
+    for sp in o.species:
+        if sp.mobile:
+            ginv = 1.0 / np.sqrt(1.0 + sp.ux.astype(np.float64) ** 2 + sp.uy.astype(np.float64) ** 2
+                                 + sp.uz.astype(np.float64) ** 2)
+            sp.vx, sp.vy, sp.vz = sp.ux * ginv, sp.uy * ginv, sp.uz * ginv
+            sp.xn = (sp.x - wl.dt * sp.vx, sp.y - wl.dt * sp.vy, sp.z - wl.dt * sp.vz)
+        else:
+            sp.xn = (sp.x, sp.y, sp.z)
+    o.deposit()
+    want = {"J+": o.J[:, 0], "J-": o.J[:, 1], "Jz": o.J[:, 2], "rho_old": o.rho_old,
+            "rho_new": o.rho_new}
+    inner = slice(3, wl.nz - 3)
+    for m in range(wl.n_modes):
+        for name, w in want.items():
+            got = sim.get_field(m, name)[:, inner]
+            ref = w[m][:, inner]
+            scale = max(np.abs(ref).max(), 1e-30)
+            assert np.abs(got - ref).max() < 5e-5 * scale, (m, name, np.abs(got - ref).max() / scale)
+
+
 def test_c0_fifty_steps_against_stored_oracle_run():
     """The same workload for 50 steps: drive moments after 1, 10, 25 and 50
     steps within relative 1e-4, field norms within 1e-4, live particle count
