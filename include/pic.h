@@ -143,11 +143,26 @@ int pic_workspace_bytes(const pic_config* cfg, const pic_species* species, int n
                         int64_t max_particles, size_t* bytes);
 
 /* Builds a context: validates, carves the workspace, builds in FP64 on the GPU
- * the [k_z] table (Eq. (5)), the k_perp grid and the Hankel matrices
- * (B_nu[i_r][i_k] = J_nu(k r), F_nu = B_nu^{-1} by Gauss-Jordan elimination),
- * uploads the particles, deposits the immobile background and zeroes E, B.
- * `hip_stream` is a hipStream_t (NULL = default stream).  Synchronizes once.
- * Errors: PIC_EINVAL, PIC_ENOSPC (workspace too small), PIC_EHIP. */
+ * the [k_z] table (Eq. (5)), the k_perp grid and the Hankel matrices of each
+ * mode m and order nu = m-1, m, m+1 (the quasi-cylindrical spectral
+ * representation of Sec. "Finite order pseudo-spectral solvers"):
+ *   backward B_nu[i_r][i_k] = J_nu(k_{i_k} r_{i_r});
+ *   forward  F_nu = Moore-Penrose pseudo-inverse of B_nu, from a one-sided
+ *            Jacobi SVD in FP64 (B_nu = U S V^T, F_nu = sum over the singular
+ *            values s_j >= 1e-4 s_max of v_j u_j^T / s_j; directions below the
+ *            cut-off are projected out, not amplified; on the J_m-zero grid
+ *            this drops the one near-null direction of order 0 in mode 1),
+ * both rounded to FP32 for the products; uploads the particles (host arrays
+ * are read during the call only), deposits the immobile background once
+ * and adds the own fields of self_field species; E, B start at zero
+ * otherwise.  `hip_stream` is a hipStream_t (NULL = default stream); the
+ * context keeps it.  Synchronizes once.
+ * Errors: PIC_EINVAL (bad cfg or species; the Jacobi SVD of a Hankel matrix
+ * did not converge within 60 sweeps; an immobile species that is not uniform
+ * in z with a moving window; the deposit tile block exceeds the device's
+ * LDS), PIC_ENOSPC (workspace smaller than pic_workspace_bytes, or more
+ * mobile particles than the capacity), PIC_EHIP.  On error *out is NULL and
+ * nothing needs freeing. */
 int pic_init(const pic_config* cfg, const pic_species* species, int n_species,
              int64_t max_particles, void* workspace, size_t bytes, void* hip_stream,
              pic_ctx** out);
@@ -156,13 +171,27 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species,
  * order returns PIC_ESTATE.  Particle storage order changes at every deposit. */
 
 /* Gathers E^n, B^n at x^n (linear shapes, 4 nodes per mode), Boris-pushes
- * u^{n-1/2} -> u^{n+1/2} and moves x^{n+1} = x^n + dt u/gamma. */
+ * u^{n-1/2} -> u^{n+1/2} and moves x^{n+1} = x^n + dt u^{n+1/2}/gamma.
+ * Fields live at integer steps and momenta at half steps, the staggering the
+ * PSATD update (1a)-(1b) assumes when it takes J at n+1/2 and rho at n, n+1
+ * (Sec. "Finite order pseudo-spectral solvers").  Asynchronous; computes each
+ * particle's new cell key for the sort.  Errors: PIC_EINVAL (null ctx),
+ * PIC_ESTATE (not at the start of a step), PIC_EHIP (launch failure). */
 int pic_gather_push(pic_ctx* ctx);
 
 /* Sorts the particles by cell, then deposits rho^n at x^n, J^{n+1/2} at
- * x^{n+1/2} with v^{n+1/2} and rho^{n+1} at x^{n+1}; the immobile background
- * density is added node by node to both densities.  Atomic-free at global
- * scope: each grid tile is written once by the workgroup that owns it. */
+ * x^{n+1/2} = x^{n+1} - dt v^{n+1/2}/2 with v^{n+1/2} and rho^{n+1} at x^{n+1}:
+ * the three source time levels of the E update (1a) and of the current
+ * correction (Sec. "Finite order pseudo-spectral solvers").  Linear shapes;
+ * mode m of a density carries exp(i m theta_p) and is divided by the ring
+ * volume 2 pi r_i dr dz; below the first radial node the inner shape node is
+ * the ghost node -dr/2, folded onto node 0 with the sign (-1)^nu of the
+ * component's Hankel order.  The immobile background density is added node by
+ * node to both densities.  Atomic-free at global scope: each grid tile is
+ * written once by the workgroup that owns it.  Asynchronous.  Errors:
+ * PIC_EINVAL (null ctx), PIC_ESTATE (gather_push not done), PIC_EHIP; a
+ * deposit work list larger than the launch sets a device flag reported as
+ * PIC_ENOSPC by the next synchronizing call. */
 int pic_deposit(pic_ctx* ctx);
 
 /* Forward FFT along z and Hankel transform of J, rho^n, rho^{n+1}; spectral

@@ -80,6 +80,17 @@ def err_emittance(eps_f, eps_inf):
     return (eps_f - eps_inf) / eps_inf
 
 
+def err_ez_pointwise(ez_f, ez_inf, floor: float = 1e-12):
+    """Eq. (13) as printed: rms over the spectral cells of the relative
+    deviation of FFT2(Ez) from the infinite-order spectrum.  Cells where the
+    reference spectrum is below floor times its maximum are skipped (the ratio
+    is undefined there); the mean runs over the remaining cells."""
+    a = np.fft.fft2(ez_f)
+    b = np.fft.fft2(ez_inf)
+    keep = np.abs(b) > floor * np.abs(b).max()
+    return float(np.sqrt(np.mean(np.abs((a[keep] - b[keep]) / b[keep]) ** 2)))
+
+
 def err_ez_normalized(ez_f, ez_inf):
     """Normalized L2 form of Eq. (13): ||FFT2(Ez_f) - FFT2(Ez_inf)|| / ||FFT2(Ez_inf)||
     (the pointwise ratio of Eq. (13) is undefined where the reference spectrum

@@ -1,7 +1,8 @@
 // Discrete Hankel transform as a batched dense product on the matrix cores.
 //
 // For one (mode, component) the radial transform is Y = A X with A an n x n
-// real matrix (forward: F_nu = B_nu^{-1}; backward: B_nu[i][k] = J_nu(k_k r_i))
+// real matrix (backward: B_nu[i][k] = J_nu(k_k r_i); forward: F_nu, the
+// pseudo-inverse of B_nu built once at set-up from an FP64 Jacobi SVD)
 // and X the [n][nz] complex field seen as an n x 2nz real matrix, so the
 // contraction runs on MFMA with the complex interleave untouched.
 //

@@ -240,3 +240,69 @@ def test_beam_field_of_a_long_relativistic_beam_closed_form():
     assert np.abs(Er[sel] - want[sel]).max() < 0.02 * np.abs(want).max()
     beta = np.sqrt(1 - 1 / gamma ** 2)
     np.testing.assert_allclose(Bt, beta * Er, rtol=0, atol=1e-10 * np.abs(Er).max())
+
+
+def test_window_shift_on_the_default_grid_within_the_retained_subspace():
+    # on the J_m-zero grid the forward transform is a pseudo-inverse F = B^+
+    # (one near-null direction of the order-0 basis of mode 1 is dropped), so
+    # P = B F projects onto the retained directions.  Removing the departed
+    # column c0 spectrally then shifting by exp(i k_z dz) synthesises to the
+    # real-space shift in every column but the head, which keeps (I - P) c0:
+    # the part of c0 the transform cannot see.  Pins the ramp's sign and the
+    # departed-column removal on the grid every workload uses
+    wl = _empty_workload(nz=32, nr=16, moving=True, kind=KPERP_JM_ZEROS)
+    sim = OracleSim(wl)
+    rng = np.random.default_rng(8)
+    shape = sim.E.shape
+    for F in (sim.Eh, sim.Bh):
+        F[:] = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    for m in range(2):
+        nus = sp.hankel_orders(m)
+        for c in range(3):
+            sim.E[m, c] = sim.hankel[m].backward(sim.Eh[m, c], nus[c])
+            sim.B[m, c] = sim.hankel[m].backward(sim.Bh[m, c], nus[c])
+    before = {"E": sim.E.copy(), "B": sim.B.copy()}
+    dropped = 0
+    sim.move_window()
+    for m in range(2):
+        hk = sim.hankel[m]
+        nus = sp.hankel_orders(m)
+        for c in range(3):
+            nu = nus[c]
+            P = hk.B[nu] @ hk.F[nu]
+            for key, Fh in (("E", sim.Eh), ("B", sim.Bh)):
+                old = before[key][m, c]
+                got = hk.backward(Fh[m, c], nu)
+                scale = np.abs(old).max()
+                np.testing.assert_allclose(got[:, :-1], old[:, 1:], atol=1e-10 * scale)
+                head = (np.eye(wl.nr) - P) @ old[:, 0]
+                np.testing.assert_allclose(got[:, -1], head, atol=1e-10 * scale)
+                # the head carries only the dropped direction, invisible to F
+                assert np.abs(hk.F[nu] @ got[:, -1]).max() < 1e-9 * scale
+                if np.abs(head).max() > 1e-12 * scale:
+                    dropped += 1
+    # mode 1, order 0 (E_-, B_- of mode 1) is the component with a dropped direction
+    assert dropped >= 2
+
+
+def test_injected_columns_continue_the_plasma_in_the_full_cycle():
+    # a neutral plasma at rest in a moving window: after several window moves
+    # (tail columns removed, lattice columns injected at the head) the
+    # electrons still deposit to -n0 on every node away from the axis and the
+    # outer edge, head and tail included, and no field appears
+    from workloads import lattice
+    nz, nr, dz, dr = 32, 12, 0.05, 0.05
+    lat = lattice(nz, nr, dz, dr, 0.0)
+    e = Species("plasma_e", -1.0, 1.0, True, inject=True, **lat)
+    i = Species("plasma_ion", 1.0, 1836.15267343, False, inject=True,
+                **{k: v.copy() for k, v in lat.items()})
+    wl = Workload("plasma", nz, nr, 2, 8, dz, dr, dz, 0.0, True, KPERP_JM_ZEROS, 3, [e, i])
+    sim = OracleSim(wl)
+    sim.step(5)
+    assert sim.zmin == pytest.approx(5 * dz)
+    s = sim.species_by_name("plasma_e")
+    assert s.x.size == nz * nr * 16
+    rho = pt.deposit_rho(2, s.q * s.w, s.x, s.y, s.z, sim.grid())
+    np.testing.assert_allclose(rho[0][1:nr - 1].real, -1.0, rtol=1e-6)
+    assert np.abs(rho[1]).max() < 1e-6
+    assert np.abs(sim.E).max() == 0.0 and np.abs(sim.B).max() == 0.0

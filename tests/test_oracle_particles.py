@@ -166,3 +166,75 @@ def test_witness_peak_current_and_density(golden_dir):
     tol = g["printed_precision"]
     assert current / 1e3 == pytest.approx(g["peak_current_kA"], rel=tol)
     assert peak_n == pytest.approx(g["peak_density_cm3"], rel=tol)
+
+
+def _axis_particles(n, seed):
+    """Particles spread over the box with a quarter of them below the first
+    radial node (r < dr/2), where the inner shape node is the ghost across
+    the axis."""
+    rng = np.random.default_rng(seed)
+    r = np.concatenate([rng.uniform(0.0, 0.5 * GRID["dr"], n // 4),
+                        rng.uniform(0.0, (GRID["nr"] - 1) * GRID["dr"], n - n // 4)])
+    th = rng.uniform(0.0, 2.0 * np.pi, n)
+    z = GRID["zmin"] + rng.uniform(0.0, GRID["nz"] * GRID["dz"], n)
+    return r * np.cos(th), r * np.sin(th), z, r
+
+
+@pytest.mark.parametrize("nu", [-1, 0, 1, 2, 3])
+def test_deposit_is_the_adjoint_of_the_gather(nu):
+    # the deposit spreads a particle quantity with the same node weights and
+    # axis rule the gather interpolates with, so for any grid field F and
+    # particle values a:  sum_nodes V_i rho_nu[i, j] F[i, j] = sum_p a_p F_nu(x_p).
+    # The gather's axis rule is pinned on its own (radially linear field,
+    # uniform field); this ties the deposit's ghost-node sign (-1)^nu to it
+    x, y, z, r = _axis_particles(400, seed=11 + nu)
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal(x.size) + 1j * rng.standard_normal(x.size)
+    F = rng.standard_normal((GRID["nr"], GRID["nz"])) + 1j * rng.standard_normal((GRID["nr"], GRID["nz"]))
+    rho = pt.deposit_scalar(a, nu, z, r, GRID["zmin"], GRID["dz"], GRID["dr"], GRID["nz"], GRID["nr"])
+    lhs = (_vol()[:, None] * rho * F).sum()
+    nodes = pt.shape_nodes(z, r, GRID["zmin"], GRID["dz"], GRID["dr"], GRID["nz"])
+    rhs = (a * pt.gather_scalar(F, nu, nodes, GRID["nr"])).sum()
+    assert abs(lhs - rhs) < 1e-12 * abs(rhs)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_odd_and_even_modes_are_regular_at_the_axis(m):
+    # a mode-m density behaves like r^|m| near the axis; with linear shapes
+    # the deposit of a single particle must therefore vanish linearly as the
+    # particle approaches the axis for odd m (ghost weight enters with -1 and
+    # cancels the node-0 weight) and stay finite, equal to the r = 0 value of
+    # e^{i m theta} q w / V_0 per z-node weight, for even m
+    th, zp = 0.6, 1.0
+    vals = []
+    radii = (1e-2, 1e-3, 1e-4)
+    for rp in radii:
+        x, y = np.array([rp * np.cos(th)]), np.array([rp * np.sin(th)])
+        rho = pt.deposit_rho(m + 1, np.array([1.0]), x, y, np.array([zp]), GRID)
+        vals.append(np.abs(rho[m][0]).sum() * _vol()[0])
+    vals = np.array(vals)
+    if m % 2:
+        # node 0 keeps (1/2 + r/dr) - (1/2 - r/dr) = 2 r/dr of the particle
+        np.testing.assert_allclose(vals, 2.0 * np.array(radii) / GRID["dr"], rtol=1e-9)
+    else:
+        np.testing.assert_allclose(vals, 1.0, rtol=1e-3)
+
+
+def test_injected_lattice_has_the_plasma_density():
+    # lattice columns as injected at the head, deposited over a full box:
+    # rho_0 = q n on every node away from the axis and the outer edge (the
+    # weights r dr/pr dz/pz 2pi/pt sum, with linear shapes, to the ring
+    # volume of each node), and the theta-symmetric lattice has no mode 1
+    nz, nr, dz, dr, zmin = GRID["nz"], GRID["nr"], GRID["dz"], GRID["dr"], GRID["zmin"]
+    density = 2.5
+    cols = [pt.lattice_column(j, zmin, nr, dz, dr, (2, 2, 4), density) for j in range(nz)]
+    x, y, z, w = (np.concatenate([c[k] for c in cols]) for k in range(4))
+    rho = pt.deposit_rho(2, -w.astype(np.float64), x, y, z, GRID)
+    np.testing.assert_allclose(rho[0][1:nr - 1].real, -density, rtol=1e-6)
+    assert np.abs(rho[1]).max() < 1e-6 * density
+    # a single injected column fills the nodes of its cell by halves
+    x, y, z, w = pt.lattice_column(nz - 1, zmin, nr, dz, dr, (2, 2, 4), density)
+    rho = pt.deposit_rho(1, w.astype(np.float64), x, y, z, GRID)
+    np.testing.assert_allclose(rho[0][1:nr - 1, nz - 1].real, 0.5 * density, rtol=1e-6)
+    np.testing.assert_allclose(rho[0][1:nr - 1, 0].real, 0.5 * density, rtol=1e-6)   # periodic wrap
+    assert np.abs(rho[0][:, 1:nz - 1]).max() == 0.0
