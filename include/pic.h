@@ -240,6 +240,25 @@ int pic_diagnostics(pic_ctx* ctx, const pic_diag_req* req, pic_diag_out* out);
 int pic_diagnostics_slices(pic_ctx* ctx, const pic_diag_req* req, pic_diag_out* out, double* sigma_gamma,
                            double* count, int32_t cap, int32_t* n_total);
 
+/* pic_diagnostics_slices for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, results and errors as pic_diagnostics_slices,
+ * except:
+ *   - its partial sums and per-slice accumulators live in one static device
+ *     array of the library (168 KB on each GPU it runs on, held until the
+ *     process ends) instead of the context's workspace; it calls no hipMalloc
+ *     or hipFree and allocates no host memory;
+ *   - at most 4096 slices: a request needing more returns PIC_ENOSPC with
+ *     *n_total set to the number needed and the moments in *out filled;
+ *   - every call on a GPU shares that GPU's array, which keeps the last call's
+ *     contents (each call clears what it accumulates); calls that overlap on
+ *     one GPU, from any context, race and must be serialized by the caller.
+ * Synchronizes.  Errors: PIC_EINVAL (null pointers, bad request), PIC_ENOSPC,
+ * PIC_EHIP (also when the array's device address could not be looked up at
+ * pic_init), PIC_ENUMERIC. */
+int pic_diagnostics_slices_noalloc(pic_ctx* ctx, const pic_diag_req* req, pic_diag_out* out,
+                                   double* sigma_gamma, double* count, int32_t cap, int32_t* n_total);
+
 /* Copies one field component of one mode to host memory ([nr][nz] complex
  * float32, 8*nr*nz bytes).  spectral = 0: real space; 1: spectral.  E, B are
  * the current fields; J, rho are those of the last deposit (spectral J is after

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "pic.h"
@@ -101,6 +102,7 @@ struct pic_ctx {
   const float** ptr_tab; // device pointer tables (see init)
   double *diag_partial, *diag_out, *diag_slices;
   int* misc;             // [0] SVD unconverged, [1..2] uniform check, [3] counter
+  double* static_scratch;// device address of the library's static diagnostics scratch on this context's GPU
   bool have_bg;
   // host mirrors
   int phase;             // 0: expect gather_push, 1: expect deposit, 2: expect spectral_push
@@ -274,6 +276,45 @@ size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
   return cv.off + kAlign;
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Static scratch of pic_diagnostics_slices_noalloc (for callers that cannot
+// allocate): block partial sums, reduced moments and per-slice accumulators
+// for at most kStaticSlices slices, 168 KB, one copy per GPU for the life of
+// the process.  In host code `scratch` is a host-side stand-in for the array,
+// not its device address: host code only ever uses the address that
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kStaticSlices = 4096;
+constexpr size_t kStaticScratchDoubles = (size_t)kDiagPartialDoubles + 32 + 4 * (size_t)kStaticSlices;
+}  // namespace
+
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices];   // per device, null until looked up
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int static_scratch_for_current_device(double** out) {
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PIC_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return PIC_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PIC_EHIP;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PIC_OK;
+}
+
 inline size_t plane_of(const pic_ctx* x) { return (size_t)x->nr * x->nz; }
 inline float2* fld(float2* base, const pic_ctx* x, int c, int m) {
   return base + ((size_t)c * x->M + m) * plane_of(x);
@@ -409,6 +450,9 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
   pic_ctx* x = new pic_ctx();   // value-initialized: every scalar member starts at zero
   x->cfg = *cfg;
   x->stream = (hipStream_t)hip_stream;
+  // the static diagnostics scratch of this GPU (null if the lookup failed:
+  // pic_diagnostics_slices_noalloc then reports PIC_EHIP, nothing else uses it)
+  (void)static_scratch_for_current_device(&x->static_scratch);
   x->M = cfg->n_modes;
   x->nz = cfg->nz;
   x->nr = cfg->nr;
@@ -866,12 +910,32 @@ int pic_get_state(pic_ctx* x, double* z_min, int64_t* steps) {
 namespace {
 // Moments of one species (two passes) and, when `slice_sigma` is given, the
 // weighted rms gamma of every slice (0 for a skipped slice).
-int diag_run(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out, std::vector<double>* slice_sigma,
-             std::vector<double>* slice_count) {
+// Device scratch of one diagnostics call: block partial sums, the reduced
+// moments and per-slice accumulators (count, weight, weighted gamma; then the
+// weighted squared deviation), room for max_slices slices.
+struct DiagScratch {
+  double* partial;
+  double* out;
+  double* slices;
+  int max_slices;
+  int too_many_slices;   // status returned when the slices exceed max_slices
+};
+
+DiagScratch workspace_diag_scratch(pic_ctx* x) {
+  return DiagScratch{x->diag_partial, x->diag_out, x->diag_slices, kMaxSlices, PIC_EINVAL};
+}
+
+// Beam moments of one species and, with sigma_gamma/count (cap entries),
+// the per-slice values; *n_total (if given) receives the slice count.  The
+// per-slice sums are brought to the host a block at a time through a fixed
+// stack buffer, so the call allocates nothing on the host either.
+int diag_run(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out, const DiagScratch& scr, double* slice_sigma,
+             double* slice_count, int cap, int32_t* n_total) {
   if (!x || !req || !out) return PIC_EINVAL;
   if (req->species < 0 || req->species >= x->n_species || !x->sp[req->species].mobile) return PIC_EINVAL;
   if (!(req->slice_len > 0) || !(req->n_sigma > 0)) return PIC_EINVAL;
   memset(out, 0, sizeof(*out));
+  if (n_total) *n_total = 0;
   hipStream_t s = x->stream;
   DiagSel sel{};
   sel.species = req->species;
@@ -879,11 +943,11 @@ int diag_run(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out, std::vector
   sel.zmin = x->cfg.z_min + (double)x->n_shift * x->cfg.dz;
   sel.inv_q = 1.0 / x->sp[req->species].q;
   const Parts& P = x->parts[x->cur];
-  launch_diag_pass1(P, x->st, sel, x->diag_partial, x->diag_out, s);
+  launch_diag_pass1(P, x->st, sel, scr.partial, scr.out, s);
   int rc = sync(x);
   if (rc) return rc;
   double a[9];
-  PIC_CK(hipMemcpy(a, x->diag_out, sizeof(a), hipMemcpyDeviceToHost));
+  PIC_CK(hipMemcpy(a, scr.out, sizeof(a), hipMemcpyDeviceToHost));
   if (rc) return rc;
   out->n = (int64_t)a[0];
   out->nan_flag = a[8] > 0 ? 1 : 0;
@@ -896,11 +960,11 @@ int diag_run(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out, std::vector
   mu.ux = a[5] / W;
   mu.uy = a[6] / W;
   mu.g = a[7] / W;
-  launch_diag_pass2(P, x->st, sel, mu, x->diag_partial, x->diag_out, s);
+  launch_diag_pass2(P, x->st, sel, mu, scr.partial, scr.out, s);
   rc = sync(x);
   if (rc) return rc;
   double b[8];
-  PIC_CK(hipMemcpy(b, x->diag_out, sizeof(b), hipMemcpyDeviceToHost));
+  PIC_CK(hipMemcpy(b, scr.out, sizeof(b), hipMemcpyDeviceToHost));
   if (rc) return rc;
   for (double& v : b) v /= W;
   out->eps_nx = sqrt(std::max(0.0, b[0] * b[1] - b[2] * b[2]));
@@ -912,32 +976,43 @@ int diag_run(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out, std::vector
   if (out->sigma_z > 0) {
     mu.slice_len = req->slice_len;
     mu.zcut = req->n_sigma * out->sigma_z;
-    double h = ceil(mu.zcut / req->slice_len);
-    if (h > kMaxSlices / 2) return PIC_EINVAL;
+    const double h = ceil(mu.zcut / req->slice_len);
+    if (h > scr.max_slices / 2) {
+      if (n_total) *n_total = h < 1e9 ? (int32_t)(2 * h) : INT32_MAX;
+      return scr.too_many_slices;
+    }
     mu.half = (int)h;
-    int ns = 2 * mu.half;
-    double* acc = x->diag_slices;
-    double* var = x->diag_slices + 3 * kMaxSlices;
+    const int ns = 2 * mu.half;
+    if (n_total) *n_total = ns;
+    double* acc = scr.slices;
+    double* var = scr.slices + 3 * (size_t)scr.max_slices;
     launch_fill_zero(acc, 3 * (size_t)ns * sizeof(double), s);
     launch_fill_zero(var, (size_t)ns * sizeof(double), s);
     launch_diag_slices(P, x->st, sel, mu, acc, var, s);
     rc = sync(x);
     if (rc) return rc;
-    std::vector<double> ha(3 * (size_t)ns), hv(ns);
-    PIC_CK(hipMemcpy(ha.data(), acc, ha.size() * sizeof(double), hipMemcpyDeviceToHost));
-    PIC_CK(hipMemcpy(hv.data(), var, hv.size() * sizeof(double), hipMemcpyDeviceToHost));
-    if (rc) return rc;
+    constexpr int kBlk = 256;
+    double ha[3 * kBlk], hv[kBlk];
     double sum = 0;
     int kept = 0;
-    if (slice_sigma) slice_sigma->assign(ns, 0.0);
-    if (slice_count) slice_count->assign(ns, 0.0);
-    for (int k = 0; k < ns; ++k) {
-      if (slice_count) (*slice_count)[k] = ha[3 * k];
-      if (ha[3 * k] < req->min_per_slice || !(ha[3 * k + 1] > 0)) continue;
-      const double sg = sqrt(hv[k] / ha[3 * k + 1]);
-      if (slice_sigma) (*slice_sigma)[k] = sg;
-      sum += sg;
-      ++kept;
+    for (int k0 = 0; k0 < ns; k0 += kBlk) {
+      const int nb = std::min(kBlk, ns - k0);
+      PIC_CK(hipMemcpy(ha, acc + 3 * (size_t)k0, 3 * (size_t)nb * sizeof(double), hipMemcpyDeviceToHost));
+      PIC_CK(hipMemcpy(hv, var + k0, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost));
+      if (rc) return rc;
+      for (int q = 0; q < nb; ++q) {
+        const int k = k0 + q;
+        const bool keep = !(ha[3 * q] < req->min_per_slice) && ha[3 * q + 1] > 0;
+        const double sg = keep ? sqrt(hv[q] / ha[3 * q + 1]) : 0.0;
+        if (k < cap) {
+          if (slice_count) slice_count[k] = ha[3 * q];
+          if (slice_sigma) slice_sigma[k] = sg;
+        }
+        if (keep) {
+          sum += sg;
+          ++kept;
+        }
+      }
     }
     out->n_slices = kept;
     out->mean_slice_sigma_gamma = kept ? sum / kept : 0.0;
@@ -947,21 +1022,23 @@ int diag_run(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out, std::vector
 }  // namespace
 
 int pic_diagnostics(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out) {
-  return diag_run(x, req, out, nullptr, nullptr);
+  if (!x) return PIC_EINVAL;
+  return diag_run(x, req, out, workspace_diag_scratch(x), nullptr, nullptr, 0, nullptr);
 }
-
 int pic_diagnostics_slices(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out, double* sigma_gamma,
                            double* count, int32_t cap, int32_t* n_total) {
   if (!x || !req || !out || !n_total || cap < 0 || (cap > 0 && (!sigma_gamma || !count))) return PIC_EINVAL;
-  std::vector<double> sg, cn;
-  const int rc = diag_run(x, req, out, &sg, &cn);
-  *n_total = (int32_t)sg.size();
-  const int n = std::min<int>((int)sg.size(), cap);
-  for (int k = 0; k < n; ++k) {
-    sigma_gamma[k] = sg[k];
-    count[k] = cn[k];
-  }
-  return rc;
+  return diag_run(x, req, out, workspace_diag_scratch(x), sigma_gamma, count, cap, n_total);
+}
+
+int pic_diagnostics_slices_noalloc(pic_ctx* x, const pic_diag_req* req, pic_diag_out* out, double* sigma_gamma,
+                                   double* count, int32_t cap, int32_t* n_total) {
+  if (!x || !req || !out || !n_total || cap < 0 || (cap > 0 && (!sigma_gamma || !count))) return PIC_EINVAL;
+  if (!x->static_scratch) return PIC_EHIP;
+  double* base = x->static_scratch;
+  const DiagScratch scr{base, base + kDiagPartialDoubles, base + kDiagPartialDoubles + 32, kStaticSlices,
+                        PIC_ENOSPC};
+  return diag_run(x, req, out, scr, sigma_gamma, count, cap, n_total);
 }
 
 int pic_free(pic_ctx* x) {

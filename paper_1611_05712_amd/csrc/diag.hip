@@ -6,7 +6,6 @@
 
 namespace pic {
 
-constexpr int kDiagBlocks = 512;
 
 __device__ __forceinline__ bool diag_alive(const Parts& p, int i, int species, const DiagSel& sel) {
   if (p.sp[i] != species) return false;
@@ -187,7 +186,7 @@ void launch_diag_slices(const Parts& p, const DevState* st, const DiagSel& sel, 
   hipLaunchKernelGGL(k_diag_slice1, dim3(kDiagBlocks), dim3(256), 0, s, p, st, sel, mu, acc);
   hipLaunchKernelGGL(k_diag_slice2, dim3(kDiagBlocks), dim3(256), 0, s, p, st, sel, mu, acc, var);
 }
-int diag_partial_doubles() { return kDiagBlocks * 9; }
+int diag_partial_doubles() { return kDiagPartialDoubles; }
 void launch_collect(const Parts& p, const DevState* st, const DiagSel& sel, int64_t cap, const Parts& out,
                     int* counter, int nmax, hipStream_t s) {
   hipLaunchKernelGGL(k_collect, dim3((nmax + 255) / 256), dim3(256), 0, s, p, st, sel, cap, out, counter);

@@ -83,7 +83,9 @@ void launch_beam_field(float2* spec, const double* kperp, const double* kzm, int
 void launch_tail_transform(const float2* tail, float2* tailhat, const float* const* ft_of_row, int nr, int nrows,
                            DevState* st, double zmin0, double dz, hipStream_t s);
 
-// diagnostics
+// diagnostics: kDiagBlocks workgroups each leave 9 partial sums
+constexpr int kDiagBlocks = 512;
+constexpr int kDiagPartialDoubles = kDiagBlocks * 9;
 int diag_partial_doubles();
 void launch_diag_pass1(const Parts& p, const DevState* st, const DiagSel& sel, double* partial, double* out,
                        hipStream_t s);

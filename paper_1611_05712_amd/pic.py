@@ -27,7 +27,7 @@ EXPORTED = (
     "pic_num_particles", "pic_get_particles", "pic_get_state", "pic_free", "pic_strerror",
     "pic_fft_z", "pic_dht_gemm", "pic_timing_enable", "pic_timing_read",
     "pic_get_tuning", "pic_set_tuning", "pic_step_graph", "pic_batch_step", "pic_autotune",
-    "pic_diagnostics_slices",
+    "pic_diagnostics_slices", "pic_diagnostics_slices_noalloc",
     "pic_mlp_num_params", "pic_mlp_workspace_bytes", "pic_mlp_init", "pic_mlp_forward", "pic_mlp_loss_grad",
     "pic_mlp_train", "pic_mlp_get_params", "pic_mlp_set_params", "pic_mlp_steps", "pic_mlp_sync", "pic_mlp_free",
 )
@@ -112,6 +112,8 @@ def load(path: str = LIB_PATH):
         getattr(L, name).argtypes = [vp]
     L.pic_step.argtypes = [vp, i32]
     L.pic_diagnostics.argtypes = [vp, ctypes.POINTER(pic_diag_req), ctypes.POINTER(pic_diag_out)]
+    L.pic_diagnostics_slices_noalloc.argtypes = [vp, ctypes.POINTER(pic_diag_req), ctypes.POINTER(pic_diag_out),
+                                                 _dp, _dp, i32, ctypes.POINTER(i32)]
     L.pic_diagnostics_slices.argtypes = [vp, ctypes.POINTER(pic_diag_req), ctypes.POINTER(pic_diag_out), _dp, _dp,
                                          i32, ctypes.POINTER(ctypes.c_int32)]
     L.pic_get_field.argtypes = [vp, i32, i32, i32, vp]
@@ -315,25 +317,27 @@ class Simulation:
         return {f: getattr(out, f) for f, _ in pic_diag_out._fields_}
 
     def diagnostics_slices(self, species, slice_len: float, n_sigma: float = 3.0, min_per_slice: int = 10,
-                           allow_nan: bool = False):
+                           allow_nan: bool = False, noalloc: bool = False):
         """pic_diagnostics plus per-slice rms gamma and counts: returns
         (moments dict, sigma_gamma[n], count[n]); slice k covers
-        xi in [(k - n/2) L, (k - n/2 + 1) L)."""
+        xi in [(k - n/2) L, (k - n/2 + 1) L).  noalloc=True calls
+        pic_diagnostics_slices_noalloc (static device scratch, at most 4096
+        slices)."""
+        name = "pic_diagnostics_slices_noalloc" if noalloc else "pic_diagnostics_slices"
+        fn = getattr(self._L, name)
         k = self.species_names.index(species) if isinstance(species, str) else int(species)
         req = pic_diag_req(k, slice_len, n_sigma, min_per_slice)
         out = pic_diag_out()
         n = ctypes.c_int32()
-        rc = self._L.pic_diagnostics_slices(self._ctx, ctypes.byref(req), ctypes.byref(out), None, None, 0,
-                                            ctypes.byref(n))
+        rc = fn(self._ctx, ctypes.byref(req), ctypes.byref(out), None, None, 0, ctypes.byref(n))
         if not (rc == PIC_OK or (allow_nan and rc == PIC_ENUMERIC)):
-            _check(rc, "pic_diagnostics_slices")
+            _check(rc, name)
         sg = np.zeros(max(n.value, 1))
         cnt = np.zeros(max(n.value, 1))
-        rc = self._L.pic_diagnostics_slices(self._ctx, ctypes.byref(req), ctypes.byref(out),
-                                            sg.ctypes.data_as(_dp), cnt.ctypes.data_as(_dp), n.value,
-                                            ctypes.byref(n))
+        rc = fn(self._ctx, ctypes.byref(req), ctypes.byref(out), sg.ctypes.data_as(_dp), cnt.ctypes.data_as(_dp),
+                n.value, ctypes.byref(n))
         if not (rc == PIC_OK or (allow_nan and rc == PIC_ENUMERIC)):
-            _check(rc, "pic_diagnostics_slices")
+            _check(rc, name)
         return {f: getattr(out, f) for f, _ in pic_diag_out._fields_}, sg[:n.value], cnt[:n.value]
 
     def timing_enable(self, on: bool = True):
