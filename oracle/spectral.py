@@ -47,10 +47,17 @@ def kz_grid(nz: int, dz: float) -> np.ndarray:
 def kz_modified(kz: np.ndarray, dz: float, order: int) -> np.ndarray:
     """Modified wavenumber [k_z] = sum_j alpha_{n,j} sin(k_z j dz)/(j dz),
     Eq. (5), with stencil order p = 2n.  order == 0 stands for the infinite
-    order (unmodified k_z)."""
+    order (unmodified k_z, zero at the Nyquist wavenumber)."""
     kz = np.asarray(kz, dtype=np.float64)
     if order == 0:
-        return kz.copy()
+        # infinite order: k_z itself, except at the z Nyquist wavenumber pi/dz,
+        # where k_z and -k_z are the same grid mode.  There the odd symbol of a
+        # first derivative must vanish (else a real field picks up an
+        # imaginary part), which is also the limit of every finite order of
+        # Eq. (5): sin(pi j) = 0 for all j.
+        out = kz.copy()
+        out[np.abs(np.abs(kz * dz) - np.pi) <= 1e-12 * np.pi] = 0.0
+        return out
     if order < 2 or order % 2:
         raise ValueError("stencil order must be even and >= 2 (or 0 for infinite)")
     n = order // 2

@@ -52,7 +52,7 @@ def resonance_kz(gamma: float, order: int, dz: float, kperp: float = 0.0) -> flo
     def f(kz):
         return float(phase_velocity_z(kz, kperp, dz, order)) - beta
 
-    grid = np.linspace(1e-6, np.pi / dz, 20001)
+    grid = np.linspace(1e-6, np.pi / dz * (1.0 - 1e-9), 20001)   # the open interval (0, pi/dz)
     vals = np.array([f(k) for k in grid])
     idx = np.nonzero(np.sign(vals[:-1]) != np.sign(vals[1:]))[0]
     if idx.size == 0:

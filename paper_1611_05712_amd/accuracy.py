@@ -76,10 +76,13 @@ def run_order(order: int, steps: int, outdir: str, marks: int = 25_000, device="
 def modified_kz(kz, dz: float, order: int):
     """[k_z] of Eq. (5), sum_j alpha_{n,j} sin(k_z j dz) / (j dz) with p = 2n; the
     coefficients of Eq. (3) by their ratio alpha_{n,j+1}/alpha_{n,j} =
-    -(n - j)/(n + j + 1) from alpha_{n,1} = 2n/(n + 1).  order 0: k_z itself."""
+    -(n - j)/(n + j + 1) from alpha_{n,1} = 2n/(n + 1).  order 0: k_z itself,
+    zero at the Nyquist wavenumber pi/dz (the limit of every finite order)."""
     kz = np.asarray(kz, np.float64)
     if order == 0:
-        return kz.copy()
+        out = kz.copy()
+        out[np.abs(np.abs(kz * dz) - np.pi) <= 1e-12 * np.pi] = 0.0   # Nyquist column
+        return out
     n = order // 2
     a = 2.0 * n / (n + 1.0)
     out = np.zeros_like(kz)
@@ -94,7 +97,7 @@ def resonance_kz(gamma: float, order: int, dz: float) -> float:
     smallest k_z in (0, pi/dz) where the numerical phase velocity [k_z]/k_z
     drops to the beam speed; NaN when there is none (infinite order)."""
     beta = np.sqrt(1.0 - 1.0 / gamma ** 2)
-    k = np.linspace(1e-6, np.pi / dz, 200_001)
+    k = np.linspace(1e-6, np.pi / dz * (1.0 - 1e-9), 200_001)   # (0, pi/dz): the Nyquist column itself is excluded
     f = modified_kz(k, dz, order) / k - beta
     idx = np.nonzero(np.sign(f[:-1]) != np.sign(f[1:]))[0]
     if idx.size == 0:

@@ -85,7 +85,11 @@ def test_kz_modified_nyquist_zero_and_convergence():
         e2 = 1 - sp.kz_modified(np.array([0.05]), 1.0, order)[0] / 0.05
         assert e1 / e2 == pytest.approx(2.0 ** order, rel=2e-2)
     kz = sp.kz_grid(64, dz)
-    assert np.array_equal(sp.kz_modified(kz, dz, 0), kz)
+    kinf = sp.kz_modified(kz, dz, 0)
+    # infinite order: k_z itself except the Nyquist column (index nz/2), zero
+    # like every finite order there
+    assert kinf[32] == 0.0 and kz[32] == pytest.approx(-np.pi / dz, rel=1e-14)
+    assert np.array_equal(np.delete(kinf, 32), np.delete(kz, 32))
     assert np.abs(sp.kz_modified(kz, dz, 256) - kz)[np.abs(kz) < 0.5 * np.pi / dz].max() < 1e-10
 
 
@@ -451,3 +455,51 @@ def test_two_binomial_passes_are_the_14641_stencil():
     got = np.fft.ifft(np.fft.fft(g) * f)
     want = (np.roll(g, 2) + 4 * np.roll(g, 1) + 6 * g + 4 * np.roll(g, -1) + np.roll(g, -2)) / 16
     np.testing.assert_allclose(got, want, atol=1e-14)
+
+
+def _real_mode0_state(nz, nr, seed):
+    """Real-space mode-0 fields of a real 3D field: scalars and z components
+    real, F_- = conj(F_+) (F_r, F_theta real)."""
+    rng = np.random.default_rng(seed)
+    def cplx():
+        return rng.standard_normal((nr, nz)) + 1j * rng.standard_normal((nr, nz))
+    out = {}
+    for name in ("E", "B", "J"):
+        fp = cplx()
+        out[name] = (fp, np.conj(fp), rng.standard_normal((nr, nz)) + 0j)
+    out["rho0"] = rng.standard_normal((nr, nz)) + 0j
+    out["rho1"] = rng.standard_normal((nr, nz)) + 0j
+    return out
+
+
+@pytest.mark.parametrize("order", [0, 8, 32])
+def test_psatd_keeps_a_real_field_real(order):
+    # mode 0 of a real field has real scalars and z components and
+    # F_- = conj(F_+); one PSATD step (forward transforms, Eqs. (1a)-(1b),
+    # inverse transforms) must keep that structure at every stencil order.
+    # At infinite order this needs a zero derivative symbol in the Nyquist
+    # column: with [k_z] = -pi/dz there, i [k_z] turns the real Nyquist
+    # coefficient of a real sequence imaginary (checked last)
+    nz, nr, dz, dt = 32, 12, 0.1, 0.1
+    st = _real_mode0_state(nz, nr, seed=order + 5)
+    hk = sp.HankelPair(0, nr, 0.1)
+    nus = sp.hankel_orders(0)
+    kp = hk.k[:, None]
+
+    def step(kzm):
+        fw = {k: tuple(hk.forward(st[k][c], nus[c]) for c in range(3)) for k in ("E", "B", "J")}
+        r0, r1 = hk.forward(st["rho0"], 0), hk.forward(st["rho1"], 0)
+        En, Bn = sp.psatd_push(fw["E"], fw["B"], fw["J"], r0, r1, dt, kp, kzm)
+        return ([hk.backward(En[c], nus[c]) for c in range(3)],
+                [hk.backward(Bn[c], nus[c]) for c in range(3)])
+
+    kzm = sp.kz_modified(sp.kz_grid(nz, dz), dz, order)[None, :]
+    E, B = step(kzm)
+    for F in (E, B):
+        scale = max(np.abs(f).max() for f in F)
+        assert np.abs(F[2].imag).max() < 1e-12 * scale
+        assert np.abs(F[1] - np.conj(F[0])).max() < 1e-12 * scale
+    if order == 0:
+        raw = sp.kz_grid(nz, dz)[None, :]          # Nyquist column left at -pi/dz
+        E, _ = step(raw)
+        assert np.abs(E[2].imag).max() > 1e-3 * np.abs(E[2]).max()
