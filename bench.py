@@ -114,32 +114,55 @@ def _traffic(kernel, workload):
     return round(e["bytes_per_launch"] / 1e9, 4)
 
 
-def cpu_baseline(wl_name, stride=8):
+def _cpu_model():
+    """Host CPU model as lscpu reports it ('' when lscpu is unavailable)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except Exception:
+        return ""
+    for line in out.splitlines():
+        if line.startswith("Model name:"):
+            return line.split(":", 1)[1].strip()
+    return ""
+
+
+def cpu_baseline(wl_name, stride=4):
     """The oracle (never tuned) timed for one PIC step on every `stride`-th
-    macro-particle of the workload, in particle-pushes/s."""
+    macro-particle of the workload, in particle-pushes/s: once with the BLAS
+    threads the host gives it (the oracle's Hankel products; its particle
+    loops are single-threaded NumPy) and once limited to one thread."""
     from oracle.cycle import OracleSim
     from workloads import preset
-    try:
-        from threadpoolctl import threadpool_info
-        blas = max([i.get("num_threads", 1) for i in threadpool_info()
-                    if i.get("user_api") == "blas"] or [1])
-    except Exception:
-        blas = 1
-    wl = preset(wl_name)
-    for s in wl.species:
-        for a in ("x", "y", "z", "ux", "uy", "uz", "w"):
-            setattr(s, a, getattr(s, a)[::stride].copy())
-        s.w = (s.w * stride).astype(s.w.dtype)
-    n_mobile = wl.n_mobile
-    o = OracleSim(wl)
-    t0 = time.perf_counter()
-    o.step(1)
-    dt = time.perf_counter() - t0
-    return {"value": n_mobile / dt, "unit": "particle-pushes/s", "cores": int(blas),
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    def blas_threads():
+        return max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+
+    def one_step():
+        wl = preset(wl_name)
+        for s in wl.species:
+            for a in ("x", "y", "z", "ux", "uy", "uz", "w"):
+                setattr(s, a, getattr(s, a)[::stride].copy())
+            s.w = (s.w * stride).astype(s.w.dtype)
+        n_mobile = wl.n_mobile
+        o = OracleSim(wl)
+        t0 = time.perf_counter()
+        o.step(1)
+        return n_mobile, time.perf_counter() - t0
+
+    threads = blas_threads()
+    n_mobile, dt = one_step()
+    with threadpool_limits(limits=1, user_api="blas"):
+        _, dt1 = one_step()
+    return {"value": n_mobile / dt, "unit": "particle-pushes/s", "cores": int(threads),
             "kind": "oracle",
+            "single_core_value": n_mobile / dt1,
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(),
             "sample": (f"one full PIC step of the {wl_name} grid with every {stride}th macro-particle "
-                       f"({n_mobile} mobile, weights x{stride}); {dt:.1f} s; particle loops are "
-                       f"single-threaded NumPy, Hankel products use {blas} BLAS threads")}
+                       f"({n_mobile} mobile, weights x{stride}): {dt:.1f} s with {threads} BLAS threads "
+                       f"(the Hankel products; particle loops are single-threaded NumPy), {dt1:.1f} s on "
+                       f"one thread; host has {os.cpu_count()} logical CPUs")}
 
 
 def scan_bench(args):

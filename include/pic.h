@@ -262,7 +262,9 @@ int pic_diagnostics_slices_noalloc(pic_ctx* ctx, const pic_diag_req* req, pic_di
 /* Copies one field component of one mode to host memory ([nr][nz] complex
  * float32, 8*nr*nz bytes).  spectral = 0: real space; 1: spectral.  E, B are
  * the current fields; J, rho are those of the last deposit (spectral J is after
- * the current correction).  Synchronizes.  Errors: PIC_EINVAL. */
+ * the current correction; the spectral transform keeps rho^{n+1} - rho^n rather
+ * than rho^n, and spectral rho^n is returned as rho^{n+1} minus it).
+ * Synchronizes.  Errors: PIC_EINVAL, PIC_EHIP. */
 int pic_get_field(pic_ctx* ctx, int mode, int comp, int spectral, void* host_dst);
 
 /* Overwrites one real-space field component of one mode from host memory

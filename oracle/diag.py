@@ -46,25 +46,42 @@ def beam_moments(x, y, z, ux, uy, uz, w, slice_len, n_sigma=3.0, min_per_slice=1
     zm = mean(z)
     sz = math.sqrt(mean((z - zm) ** 2))
     out["z_mean"], out["sigma_z"] = zm, sz
-    xi = z - zm
-    h = int(math.ceil(n_sigma * sz / slice_len)) if sz > 0 else 0
-    sel = np.abs(xi) <= n_sigma * sz
-    sidx = np.floor(xi[sel] / slice_len).astype(np.int64) + h
-    spreads = []
-    gs, ws = g[sel], w[sel]
-    for s in range(2 * h):
-        mk = sidx == s
-        if mk.sum() < min_per_slice:
-            continue
-        ww = ws[mk]
-        Ws = ww.sum()
-        gm = (ww * gs[mk]).sum() / Ws
-        spreads.append(math.sqrt((ww * (gs[mk] - gm) ** 2).sum() / Ws))
+    sg, cnt = slice_spreads(z, g, w, slice_len, n_sigma, min_per_slice)
+    spreads = [v for v, c in zip(sg, cnt) if c >= min_per_slice]
     out["n_slices"] = len(spreads)
     out["mean_slice_sigma_gamma"] = float(np.mean(spreads)) if spreads else 0.0
     finite = all(np.isfinite(a).all() for a in (x, y, z, ux, uy, uz))
     out["nan_flag"] = 0 if finite else 1
     return out
+
+
+def slice_spreads(z, gamma, w, slice_len, n_sigma=3.0, min_per_slice=10):
+    """Per-slice weighted rms gamma and macro-particle count of the slices of
+    beam_moments: slice s covers xi = z - <z> in [(s - h) L, (s - h + 1) L),
+    s = 0 .. 2h - 1, h = ceil(n_sigma sigma_z / L), particles with
+    |xi| <= n_sigma sigma_z only; the spread is 0 for a slice with fewer than
+    min_per_slice particles."""
+    z, g, w = (np.asarray(a, np.float64) for a in (z, gamma, w))
+    W = w.sum()
+    zm = float((w * z).sum() / W)
+    sz = math.sqrt(float((w * (z - zm) ** 2).sum() / W))
+    h = int(math.ceil(n_sigma * sz / slice_len)) if sz > 0 else 0
+    xi = z - zm
+    sel = np.abs(xi) <= n_sigma * sz
+    sidx = np.floor(xi[sel] / slice_len).astype(np.int64) + h
+    gs, ws = g[sel], w[sel]
+    sg = np.zeros(2 * h)
+    cnt = np.zeros(2 * h, np.int64)
+    for k in range(2 * h):
+        mk = sidx == k
+        cnt[k] = int(mk.sum())
+        if cnt[k] < min_per_slice:
+            continue
+        ww = ws[mk]
+        Ws = ww.sum()
+        gm = (ww * gs[mk]).sum() / Ws
+        sg[k] = math.sqrt((ww * (gs[mk] - gm) ** 2).sum() / Ws)
+    return sg, cnt
 
 
 def err_sigma_gamma(slice_f, slice_inf):

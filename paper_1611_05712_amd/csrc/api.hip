@@ -60,6 +60,13 @@ __global__ void k_apply_shift(float2* spec, const float2* tw, const float2* tail
   spec[idx] = cmul(ph, csub(spec[idx], tailhat[cm * nr + ik]));
 }
 
+// out = a - b over n complex values (the spectral rho^n from the stored
+// rho^{n+1} and rho^{n+1} - rho^n)
+__global__ void k_csub(float2* out, const float2* a, const float2* b, int64_t n) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) out[idx] = csub(a[idx], b[idx]);
+}
+
 }  // namespace pic
 
 // ---------------------------------------------------------------------------
@@ -93,8 +100,9 @@ struct pic_ctx {
   int *count, *offset, *cursor, *bsum;
   int *dep_nchunk, *dep_start;
   float2* dep_partial;
-  float2 *real, *spec, *tmp, *bg, *tail, *tailhat;
-  float2* gfield;        // node-interleaved real-space E, B for the gather: [r][z][m][6]   // bg: real-space immobile density [m][r][z]
+  float2 *real, *spec, *tmp, *tail, *tailhat;
+  float2* gfield;        // node-interleaved real-space E, B for the gather: [r][z][m][6]
+  double* ionblk;        // FP64 immobile-background block of every deposit tile
   double *kz, *kzm, *kperp;
   float2* tw;
   float* mats;           // [m][order slot 0..2][dir 0 fwd / 1 bwd][nr][nr], transposed
@@ -104,6 +112,7 @@ struct pic_ctx {
   int* misc;             // [0] SVD unconverged, [1..2] uniform check, [3] counter
   double* static_scratch;// device address of the library's static diagnostics scratch on this context's GPU
   bool have_bg;
+  bool rho_carry;        // the last deposit's rho^{n+1} is the next step's rho^n (shifted with the window)
   // host mirrors
   int phase;             // 0: expect gather_push, 1: expect deposit, 2: expect spectral_push
   bool eb_stale;
@@ -226,7 +235,7 @@ size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
   float2* real = cv.take<float2>(kNumComp * M * plane);
   float2* spec = cv.take<float2>(kNumComp * M * plane);
   float2* tmp = cv.take<float2>(kNumComp * M * plane);
-  float2* bg = cv.take<float2>(M * plane);
+  double* ionblk = cv.take<double>((size_t)dep.ntiles * dep.ion_doubles);
   float2* gfield = cv.take<float2>(6 * M * plane);
   float2* tail = cv.take<float2>(6 * M * nr);
   float2* tailhat = cv.take<float2>(6 * M * nr);
@@ -257,7 +266,7 @@ size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
     x->real = real;
     x->spec = spec;
     x->tmp = tmp;
-    x->bg = bg;
+    x->ionblk = ionblk;
     x->tail = tail;
     x->gfield = gfield;
     x->tailhat = tailhat;
@@ -378,13 +387,20 @@ struct Phase {
   }
 };
 
-// forward transform: real[c0 .. c0+nc) -> tmp (FFT) -> spec (DHT)
+// forward transform: real[c0 .. c0+nc) -> tmp (FFT) -> spec (DHT).  With the
+// sources, the rho^n slot is transformed as rho^{n+1} - rho^n: the current
+// correction and the PSATD charge terms need that difference, an order of
+// magnitude below rho itself in a wake, and taking it before the transforms
+// keeps their FP32 rounding relative to it rather than to rho.
 void forward_transform(pic_ctx* x, float2* src_base, int c0, int nc, int pt_entry) {
   const int M = x->M;
   {
     Phase ph(x, PIC_T_FFT_FWD);
-    launch_fft(fld(src_base, x, c0, 0), fld(x->tmp, x, c0, 0), x->tw, x->nz, (int64_t)nc * M * x->nr, false, false,
-               nullptr, x->stream);
+    const int64_t plane_rows = (int64_t)M * x->nr;
+    const bool src = c0 == kCompJ;
+    const int64_t lo = src ? (kCompRho0 - kCompJ) * plane_rows : 0;
+    launch_fft(fld(src_base, x, c0, 0), fld(x->tmp, x, c0, 0), x->tw, x->nz, (int64_t)nc * plane_rows, false, false,
+               nullptr, x->stream, lo, src ? lo + plane_rows : 0, plane_rows);
   }
   const float* const* tab = x->ptr_tab + pt_entry;
   int batch = nc * M;
@@ -515,7 +531,7 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
   launch_fill_zero(x->count, (size_t)(g.ncells + 2) * sizeof(int), s);
   launch_fill_zero(x->real, kNumComp * M * plane * sizeof(float2), s);
   launch_fill_zero(x->spec, kNumComp * M * plane * sizeof(float2), s);
-  launch_fill_zero(x->bg, M * plane * sizeof(float2), s);
+  launch_fill_zero(x->ionblk, (size_t)x->dep.ntiles * x->dep.ion_doubles * sizeof(double), s);
   launch_fill_zero(x->gfield, 6 * M * plane * sizeof(float2), s);
   launch_fill_zero(x->tailhat, 6 * M * nr * sizeof(float2), s);
   launch_fill_zero(x->misc, 16 * sizeof(int), s);
@@ -594,15 +610,18 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
     launch_keys(P, g, x->st, x->key, x->count, (int)cap, s);
     launch_scan(x->count, g.ncells + 1, x->bsum, x->offset, x->cursor, g.ncells, x->st, s);
     launch_scatter(P, x->parts[0], x->key, x->cursor, x->st, g.ncells, (int)cap, s);
-    launch_deposit(x->parts[0], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real, nullptr, g,
-                   x->st, kDepAll, s);
     if (cfg->moving_window) {
+      // the window moves over a background that must look the same from every
+      // position: check its deposited density is uniform in z
+      launch_deposit(x->parts[0], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real, nullptr,
+                     nullptr, g, x->st, kDepAll, kRhoDeposit, s);
       launch_uniform_check(fld(x->real, x, kCompJ + 4, 0), M * nr, nz, (unsigned*)(x->misc + 1), s);
+      launch_fill_zero(x->real, kNumComp * M * plane * sizeof(float2), s);
     }
-    // keep the real-space background density: every deposit adds it node by node
-    PIC_CK(hipMemcpyAsync(x->bg, fld(x->real, x, kCompJ + 4, 0), M * plane * sizeof(float2),
-                          hipMemcpyDeviceToDevice, s));
-    launch_fill_zero(x->real, kNumComp * M * plane * sizeof(float2), s);
+    // keep the background as FP64 blocks of the deposit tiles: every deposit
+    // adds them to its tile blocks before rounding to FP32
+    launch_deposit(x->parts[0], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real, nullptr,
+                   x->ionblk, g, x->st, kDepAll, kRhoDeposit, s);
   }
 
   // -------- own fields of the beams flagged self_field: each beam alone is
@@ -639,7 +658,7 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
       launch_scan(x->count, g.ncells + 1, x->bsum, x->offset, x->cursor, g.ncells, x->st, s);
       launch_scatter(P, x->parts[0], x->key, x->cursor, x->st, g.ncells, (int)cap, s);
       launch_deposit(x->parts[0], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real, nullptr,
-                     g, x->st, kDepAll, s);
+                     nullptr, g, x->st, kDepAll, kRhoDeposit, s);
       forward_transform(x, x->real, kCompJ, kNumSrc, x->pt_fwd_src);
       launch_beam_field(x->spec, x->kperp, x->kzm, nz, nr, M, gam, beta, s);
     }
@@ -727,14 +746,18 @@ int pic_deposit(pic_ctx* x) {
                    x->stream);
   }
   x->cur ^= 1;
-  const float2* bg = x->have_bg ? x->bg : nullptr;
+  const double* ion = x->have_bg ? x->ionblk : nullptr;
+  // rho^n: the same particles at the same positions as the last deposit's
+  // rho^{n+1} when that deposit was this context's previous step
+  const int rho_mode = !x->rho_carry ? kRhoDeposit : x->cfg.moving_window ? kRhoCarryShift : kRhoCarry;
   const int stage[3] = {kDepPlan, kDepTiles, kDepCombine};
   const int timer[3] = {PIC_T_DEP_PLAN, PIC_T_DEPOSIT, PIC_T_DEP_COMBINE};
   for (int k = 0; k < 3; ++k) {
     Phase ph(x, timer[k]);
-    launch_deposit(x->parts[x->cur], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real, bg,
-                   g, x->st, stage[k], x->stream);
+    launch_deposit(x->parts[x->cur], x->offset, x->dep, x->dep_nchunk, x->dep_start, x->dep_partial, x->real, ion,
+                   nullptr, g, x->st, stage[k], rho_mode, x->stream);
   }
+  x->rho_carry = true;
   x->phase = 2;
   return check_launch();
 }
@@ -744,6 +767,7 @@ int pic_spectral_push(pic_ctx* x) {
   bool sources_set = true;
   for (int m = 0; m < x->M; ++m) sources_set = sources_set && (x->src_set[m] == 0x1Fu);
   if (x->phase != 2 && !(x->phase == 0 && sources_set)) return PIC_ESTATE;
+  if (x->phase == 0) x->rho_carry = false;   // sources given by the caller, not deposited
   hipStream_t s = x->stream;
   const int M = x->M, nr = x->nr, nz = x->nz;
   bool apply_shift = x->spec_pending;
@@ -878,6 +902,16 @@ int pic_get_field(pic_ctx* x, int mode, int comp, int spectral, void* host_dst) 
   int rc = sync(x);
   if (rc) return rc;
   const float2* src = fld(spectral ? x->spec : x->real, x, comp, mode);
+  if (spectral && comp == kCompRho0) {
+    // the slot holds rho^{n+1} - rho^n; the transform buffer is free between steps
+    float2* t = fld(x->tmp, x, kCompRho0, mode);
+    const int64_t n = plane_of(x);
+    hipLaunchKernelGGL(k_csub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, x->stream, t,
+                       fld(x->spec, x, kCompRho0 + 1, mode), src, n);
+    rc = sync(x);
+    if (rc) return rc;
+    src = t;
+  }
   if (hipMemcpy(host_dst, src, plane_of(x) * sizeof(float2), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
   return PIC_OK;
 }
@@ -896,6 +930,7 @@ int pic_set_field(pic_ctx* x, int mode, int comp, const void* host_src) {
     if (rc) return rc;
   } else {
     x->src_set[mode] |= 1u << (comp - kCompJ);
+    x->rho_carry = false;   // the next deposit's rho^n comes from the particles again
   }
   return PIC_OK;
 }
@@ -1083,7 +1118,7 @@ int capture_graph(pic_ctx* x) {
   }
   const int cur = x->cur, phase = x->phase;
   const int64_t steps = x->steps, n_shift = x->n_shift;
-  const bool spec_pending = x->spec_pending, eb_stale = x->eb_stale;
+  const bool spec_pending = x->spec_pending, eb_stale = x->eb_stale, rho_carry = x->rho_carry;
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PIC_EHIP;
   int rc = pic_step(x, 2);
@@ -1094,6 +1129,7 @@ int capture_graph(pic_ctx* x) {
   x->n_shift = n_shift;
   x->spec_pending = spec_pending;
   x->eb_stale = eb_stale;
+  x->rho_carry = rho_carry;
   if (rc != PIC_OK || e != hipSuccess || !g) {
     if (g) (void)hipGraphDestroy(g);
     (void)hipGetLastError();
@@ -1117,8 +1153,9 @@ int graph_steps(pic_ctx* x, int n) {
     if (x->src_set[m]) return PIC_ESTATE;
   int rc = PIC_OK;
   // one eager step settles the one-time work (re-transform of set fields,
-  // first window shift, kernel attributes)
-  if (n > 0 && (x->steps == 0 || x->eb_stale)) {
+  // first window shift, kernel attributes, a rho^n that cannot be carried
+  // over), so that every captured step is an ordinary one
+  if (n > 0 && (x->steps == 0 || x->eb_stale || !x->rho_carry)) {
     rc = pic_step(x, 1);
     if (rc) return rc;
     --n;

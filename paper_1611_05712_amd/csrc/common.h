@@ -11,6 +11,7 @@ constexpr int kMaxSpecies = 16;
 constexpr int kNumComp = 11;           // E+,E-,Ez,B+,B-,Bz,J+,J-,Jz,rho^n,rho^{n+1}
 constexpr int kCompJ = 6;              // first source component
 constexpr int kNumSrc = 5;             // J+,J-,Jz,rho^n,rho^{n+1}
+constexpr int kCompRho0 = 9;           // rho^n (spectral slot: rho^{n+1} - rho^n)
 constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;
 // The forward discrete Hankel transform is the pseudo-inverse of the Bessel
 // synthesis matrix: singular values below this fraction of the largest are

@@ -24,6 +24,12 @@
 // particles per cell cost one flush per run rather than one atomic per
 // particle.  Waves whose particles are all at rest skip the current and reuse
 // the x^{n+1} shape for rho^n.
+//
+// Immobile background: the ion deposit of each tile is kept as an FP64 block
+// (built once at set-up by this same kernel) and added to both densities in
+// the LDS block of the tile's first work item before the FP32 rounding, so
+// the rounding acts on the net charge, not on two order-one densities that
+// nearly cancel.
 #include "common.h"
 #include "launch.h"
 
@@ -31,8 +37,8 @@ namespace pic {
 
 constexpr int kChunkMin = 2048;  // smallest chunk of a dense tile (sizes the work list)
 constexpr int kChunkMax = 8192;  // largest chunk (keeps a work item's run table in 16 bits)
-constexpr int kTZ = 32;
-constexpr int kRun = 8;       // consecutive particles per lane per sub-chunk
+constexpr int kTZ = 32;          // tile rows (z)
+constexpr int kRun = 8;          // particles of one cell per lane per run
 
 __device__ __forceinline__ size_t dfidx(int c, int m, int M, int nr, int nz) {
   return ((size_t)c * M + m) * (size_t)nr * nz;
@@ -314,6 +320,49 @@ __device__ __forceinline__ void acc_step(double* __restrict__ lds, Acc<K>& A, ui
   }
 }
 
+// Two accumulators for one position kind (the current J^{n+1/2}): the
+// particles of one x^{n+1} cell have their x^{n+1/2} in at most a few cells
+// (the run's cell and a neighbour the faster particles crossed from), so a
+// particle goes to the slot holding its cell and a flush happens only when a
+// third cell appears (then the slot not hit last is flushed and reused).
+// Each slot adds w times the values with w = 0 or 1, so both slots stay in
+// one register set without branches.
+template <int K>
+struct Acc2 {
+  Acc<K> a, b;
+  bool last_b;   // the last particle went to slot b
+};
+
+template <int TR, int H, int K, class Set, class OffFn>
+__device__ __forceinline__ void acc2_step(double* __restrict__ lds, Acc2<K>& A, uint32_t key, const float (&v)[K],
+                                          const ShapePos& s, const Grid& g, int J0, int C0, OffFn off) {
+  const bool hit_a = key == A.a.key, hit_b = key == A.b.key;
+  if (!hit_a && !hit_b) {
+    // a third cell: flush the slot not hit last and give it this cell
+    Acc<K>& victim = A.last_b ? A.a : A.b;
+    if (victim.key != kInvalidKey) acc_flush<TR, H, K, Set>(lds, victim, g, J0, C0, off);
+    acc_reset(victim, key);
+  }
+  const bool to_b = key == A.b.key;
+  A.last_b = to_b;
+  const float fb = to_b ? 1.f : 0.f, fa = 1.f - fb;
+  const float fz = s.fz, fr = s.fr;
+  const float w0 = (1.f - fz) * (1.f - fr), w1 = fz * (1.f - fr), w2 = (1.f - fz) * fr, w3 = fz * fr;
+  const float a0 = fa * w0, a1 = fa * w1, a2 = fa * w2, a3 = fa * w3;
+  const float b0 = fb * w0, b1 = fb * w1, b2 = fb * w2, b3 = fb * w3;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    A.a.a[4 * k + 0] = fmaf(a0, v[k], A.a.a[4 * k + 0]);
+    A.a.a[4 * k + 1] = fmaf(a1, v[k], A.a.a[4 * k + 1]);
+    A.a.a[4 * k + 2] = fmaf(a2, v[k], A.a.a[4 * k + 2]);
+    A.a.a[4 * k + 3] = fmaf(a3, v[k], A.a.a[4 * k + 3]);
+    A.b.a[4 * k + 0] = fmaf(b0, v[k], A.b.a[4 * k + 0]);
+    A.b.a[4 * k + 1] = fmaf(b1, v[k], A.b.a[4 * k + 1]);
+    A.b.a[4 * k + 2] = fmaf(b2, v[k], A.b.a[4 * k + 2]);
+    A.b.a[4 * k + 3] = fmaf(b3, v[k], A.b.a[4 * k + 3]);
+  }
+}
+
 // one particle's deposit inputs
 struct PLoad {
   double x = 0.0, y = 0.0, z = 0.0, uz = 0.0;
@@ -329,41 +378,70 @@ struct PLoad {
   }
 };
 
-template <int TR, int H, int M>
+// number of rho values per node (mode 0 real, complex from mode 1 on)
+template <int M>
+struct RhoVals {
+  static constexpr int N = 1 + 2 * (M - 1);
+};
+
+// What a launch of the tile kernel deposits:
+//   kDepFull   rho^n, J^{n+1/2} and rho^{n+1} of every work item;
+//   kDepCarry  J^{n+1/2} and rho^{n+1} only: rho^n is the previous step's
+//              rho^{n+1} carried over (the same particles at the same
+//              positions), re-deposited only in the edge tiles (kDepEdgeRho);
+//   kDepEdgeRho rho^n of the two tile rows at the ends of the window along z
+//              (one workgroup per tile, all its particles), written into the
+//              rho^n part of the tile's first slot after kDepCarry: these
+//              hold the nodes the window move changes (particles that left
+//              behind the window, the column injected at the head);
+//   kDepIon    set-up of the immobile background: FP64 rho^{n+1} blocks.
+enum DepMode { kDepFull = 0, kDepCarry = 1, kDepEdgeRho = 2, kDepIon = 3 };
+
+// Otherwise the first work item of each tile adds the tile's FP64 background
+// block `ionblk` (when given) to the densities it deposits.
+template <int TR, int H, int M, int MODE>
 __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict__ offset,
                                                  const int* __restrict__ nchunk, const int* __restrict__ chunk_start,
-                                                 float* __restrict__ scratch, Grid g, TileGeom tg, DevState* st) {
+                                                 float* __restrict__ scratch, const double* __restrict__ ionblk, Grid g,
+                                                 TileGeom tg, DevState* st) {
   using B = Blk<TR, H>;
   using RS = RhoSet<M, B::NODES>;
   using JS = JSet<M, B::NODES>;
+  constexpr bool kRhoN = MODE == kDepFull || MODE == kDepEdgeRho || MODE == kDepIon;
+  constexpr bool kRho1J = MODE != kDepEdgeRho;
   extern __shared__ double lds[];
-  constexpr int kCells = kTZ * TR;              // cells (key columns x rows) of a tile
-  __shared__ int rowstart[kTZ];
-  __shared__ int rowpref[kTZ + 1];
-  __shared__ uint16_t runpref[kCells + 1];      // runs of <= kRun particles before each cell
+  constexpr int nacc = Vals<M>::N * B::NODES;
+  constexpr int kCells = kTZ * TR;   // cells (key columns x rows) of a tile
+  __shared__ int rowstart[kTZ];      // sorted index of each tile row's first particle
+  __shared__ int rowpref[kTZ + 1];   // tile-local index of each row's first particle
+  __shared__ uint16_t runpref[kCells + 1];   // runs of <= kRun particles before each cell
   __shared__ int wsum[4];
   __shared__ int s_tile;
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
-  if (b == 0 && tid == 0) {
+  if (MODE != kDepIon && MODE != kDepEdgeRho && b == 0 && tid == 0) {
     st->n_part = st->n_live;
     if (chunk_start[tg.ntiles] > (int)gridDim.x) st->overflow = 2;   // work list larger than the launch
   }
-  if (b >= chunk_start[tg.ntiles]) return;   // uniform per workgroup
-  if (tid == 0) {
-    int lo = 0, hi = tg.ntiles;   // chunk_start[lo] <= b < chunk_start[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (chunk_start[mid] <= b) lo = mid;
-      else hi = mid;
+  if (MODE == kDepEdgeRho) {
+    // edge tiles: tz = 0 and tz = ntz - 1 of every radial tile column
+    if (tid == 0) s_tile = (b >> 1) * tg.ntz + ((b & 1) ? tg.ntz - 1 : 0);
+  } else {
+    if (b >= chunk_start[tg.ntiles]) return;   // uniform per workgroup
+    if (tid == 0) {
+      int lo = 0, hi = tg.ntiles;   // chunk_start[lo] <= b < chunk_start[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (chunk_start[mid] <= b) lo = mid;
+        else hi = mid;
+      }
+      s_tile = lo;
     }
-    s_tile = lo;
   }
-  constexpr int nacc = Vals<M>::N * B::NODES;
   for (int e = tid; e < nacc; e += blockDim.x) lds[e] = 0.0;
   __syncthreads();
   const int t = s_tile;
-  const int chunk = b - chunk_start[t];
+  const int chunk = MODE == kDepEdgeRho ? 0 : b - chunk_start[t];
   const int J0 = (t % tg.ntz) * kTZ, C0 = (t / tg.ntz) * TR;
   const int C1 = min(C0 + TR, g.ncol);
   if (tid < kTZ) {
@@ -379,149 +457,234 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
   }
   __syncthreads();
   const int total = rowpref[kTZ];
-  const bool whole = nchunk[t] == 1;
-  const int f0 = whole ? 0 : chunk * tg.chunk;
-  const int f1 = whole ? total : min(total, f0 + tg.chunk);
   const double zmin = st->zmin;
   const double dt = g.dt;
-  // Runs: every cell's particles (clipped to this chunk) are cut into runs of
-  // at most kRun, so a run never leaves its cell of x^{n+1}.  runpref is the
-  // exclusive prefix of the run counts over the tile's cells.
-  auto cell_range = [&](int c, int& lo, int& hi) {
-    const int row = c / TR, col = c % TR;
-    lo = hi = 0;
-    if (C0 + col < C1) {
-      const int* o = offset + (J0 + row) * g.ncol + C0 + col;
-      lo = max(f0, rowpref[row] + (o[0] - rowstart[row]));
-      hi = min(f1, rowpref[row] + (o[1] - rowstart[row]));
-    }
-  };
-  {
-    static_assert(kCells % 256 == 0 && kCells <= 512, "tile cells per thread");
-    constexpr int per = kCells / 256;
-    int nrun[per], tot = 0;
-#pragma unroll
-    for (int q = 0; q < per; ++q) {
-      int lo, hi;
-      cell_range(tid * per + q, lo, hi);
-      nrun[q] = hi > lo ? (hi - lo + kRun - 1) / kRun : 0;
-      tot += nrun[q];
-    }
-    // block-wide exclusive scan of the per-thread totals
-    const int lane = tid & 63, wave = tid >> 6;
-    int inc = tot;
-    for (int d = 1; d < 64; d <<= 1) {
-      const int u = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += u;
-    }
-    if (lane == 63) wsum[wave] = inc;
-    __syncthreads();
-    int excl = inc - tot;
-    for (int w = 0; w < wave; ++w) excl += wsum[w];
-#pragma unroll
-    for (int q = 0; q < per; ++q) {
-      runpref[tid * per + q] = (uint16_t)excl;
-      excl += nrun[q];
-    }
-    if (tid == 255) runpref[kCells] = (uint16_t)excl;
-    __syncthreads();
+  // Particle range of this work item: one chunk of a dense tile, or the whole
+  // tile.  The edge pass takes its whole tile in pieces of one chunk.
+  const int npiece = MODE == kDepEdgeRho ? max(1, (total + tg.chunk - 1) / tg.chunk) : 1;
+  int f0 = 0, f1 = total;
+  if (MODE != kDepEdgeRho && nchunk[t] != 1) {
+    f0 = chunk * tg.chunk;
+    f1 = min(total, f0 + tg.chunk);
   }
-  const int nruns = runpref[kCells];
   Acc<RS::K> An, A1;
-  Acc<JS::K> AJ;
+  Acc2<JS::K> AJ;
   acc_reset(An, kInvalidKey);
   acc_reset(A1, kInvalidKey);
-  acc_reset(AJ, kInvalidKey);
-  // Round r0: thread tid takes run r0 + tid.  All lanes start their runs
-  // together, so the rho^{n+1} accumulator (whose cell is the run's cell)
-  // flushes at most once per round; rho^n and J flush when their own cell
-  // changes.  A lane keeps its accumulators across rounds (a beam cell with
-  // thousands of particles gives one lane consecutive runs of one cell).
-  for (int r0 = 0; r0 < nruns; r0 += 256) {
-    const int r = r0 + tid;
-    int len = 0, idx0 = 0;
-    uint32_t rkey = A1.key;
-    if (r < nruns) {
-      int lo = 0, hi = kCells;   // runpref[lo] <= r < runpref[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if ((int)runpref[mid] <= r) lo = mid;
-        else hi = mid;
-      }
-      int a, e;
-      cell_range(lo, a, e);
-      const int start = a + (r - (int)runpref[lo]) * kRun;
-      len = min(kRun, e - start);
-      const int row = lo / TR, col = lo % TR;
-      idx0 = rowstart[row] + (start - rowpref[row]);
-      rkey = (uint32_t)(J0 + row) * 2048u + (uint32_t)(C0 + col);
+  acc_reset(AJ.a, kInvalidKey);
+  acc_reset(AJ.b, kInvalidKey);
+  AJ.last_b = true;
+  for (int piece = 0; piece < npiece; ++piece) {
+    if (MODE == kDepEdgeRho) {
+      f0 = piece * tg.chunk;
+      f1 = min(total, f0 + tg.chunk);
     }
-    if (rkey != A1.key) {
-      if (A1.key != kInvalidKey) acc_flush<TR, H, RS::K, RS>(lds, A1, g, J0, C0, [](int k) { return RS::off(4, k); });
-      acc_reset(A1, rkey);
-    }
-    // particle data of the next iteration is loaded before the current one
-    // is processed, so its latency overlaps the arithmetic
-    PLoad nx;
-    if (len > 0) nx.load(p, idx0);
-    for (int it = 0; it < kRun; ++it) {
-      const bool valid = it < len;
-      const PLoad cur = nx;
-      if (it + 1 < len) nx.load(p, idx0 + it + 1);
-      double x = 0.0, y = 0.0, z = zmin;
-      float ux = 0.f, uy = 0.f, uz = 0.f, qw = 0.f;
-      if (valid) {
-        x = cur.x;
-        y = cur.y;
-        z = cur.z;
-        ux = cur.ux;
-        uy = cur.uy;
-        uz = (float)cur.uz;
-        qw = cur.w;
+    // Runs: every cell's particles (clipped to [f0, f1)) are cut into runs of
+    // at most kRun, so a run never leaves its cell of x^{n+1}; runpref is the
+    // exclusive prefix of the run counts over the tile's cells.
+    auto cell_range = [&](int c, int& lo, int& hi) {
+      const int row = c / TR, col = c % TR;
+      lo = hi = 0;
+      if (C0 + col < C1) {
+        const int* o = offset + (J0 + row) * g.ncol + C0 + col;
+        lo = max(f0, rowpref[row] + (o[0] - rowstart[row]));
+        hi = min(f1, rowpref[row] + (o[1] - rowstart[row]));
       }
-      const bool cold = __ballot(valid && (ux != 0.f || uy != 0.f || uz != 0.f)) == 0;
-      const float ginv = 1.f / sqrtf(1.f + ux * ux + uy * uy + uz * uz);
-      const float vx = ux * ginv, vy = uy * ginv, vz = uz * ginv;
-      // rho^{n+1} at x^{n+1}, in the run's cell (particles beyond the last
-      // radial node share the last key column and deposit nothing); rho^n
-      // too when the whole wave is at rest
-      {
-        const ShapePos s = shape_at(x, y, z, zmin, g);
-        const uint32_t key = valid ? pos_key(s, g.nr) : A1.key;
-        float v[RS::K];
-        RS::values(valid && s.i0 < g.nr ? qw : 0.f, s.eith, v);
-        acc_add(A1, v, s.fz, s.fr);
-        if (cold) {
-          const uint32_t key0 = valid ? key : An.key;
-          acc_step<TR, H, RS::K, RS>(lds, An, key0, v, s, g, J0, C0, [](int k) { return RS::off(3, k); });
-          continue;
+    };
+    __syncthreads();   // the previous piece's table is no longer read
+    {
+      static_assert(kCells % 256 == 0 && kCells <= 512, "tile cells per thread");
+      constexpr int per = kCells / 256;
+      int nrun[per], tot = 0;
+#pragma unroll
+      for (int q = 0; q < per; ++q) {
+        int lo, hi;
+        cell_range(tid * per + q, lo, hi);
+        nrun[q] = hi > lo ? (hi - lo + kRun - 1) / kRun : 0;
+        tot += nrun[q];
+      }
+      // block-wide exclusive scan of the per-thread totals
+      const int lane = tid & 63, wave = tid >> 6;
+      int inc = tot;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += u;
+      }
+      if (lane == 63) wsum[wave] = inc;
+      __syncthreads();
+      int excl = inc - tot;
+      for (int w = 0; w < wave; ++w) excl += wsum[w];
+#pragma unroll
+      for (int q = 0; q < per; ++q) {
+        runpref[tid * per + q] = (uint16_t)excl;
+        excl += nrun[q];
+      }
+      if (tid == 255) runpref[kCells] = (uint16_t)excl;
+      __syncthreads();
+    }
+    const int nruns = runpref[kCells];
+    // Round r0: thread tid takes run r0 + tid.  All lanes start their runs
+    // together, so the rho^{n+1} accumulator (whose cell is the run's cell)
+    // flushes at most once per round; J keeps two cells (the cells its
+    // half-step positions fall in) and flushes one only when a third appears;
+    // rho^n flushes when its cell changes.  A lane keeps its accumulators
+    // across rounds (a beam cell with thousands of particles gives one lane
+    // consecutive runs of one cell).
+    for (int r0 = 0; r0 < nruns; r0 += 256) {
+      const int r = r0 + tid;
+      int len = 0, idx0 = 0;
+      uint32_t rkey = A1.key;
+      if (r < nruns) {
+        int lo = 0, hi = kCells;   // runpref[lo] <= r < runpref[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if ((int)runpref[mid] <= r) lo = mid;
+          else hi = mid;
+        }
+        int a, e;
+        cell_range(lo, a, e);
+        const int start = a + (r - (int)runpref[lo]) * kRun;
+        len = min(kRun, e - start);
+        const int row = lo / TR, col = lo % TR;
+        idx0 = rowstart[row] + (start - rowpref[row]);
+        rkey = (uint32_t)(J0 + row) * 2048u + (uint32_t)(C0 + col);
+      }
+      if (kRho1J && rkey != A1.key) {
+        if (A1.key != kInvalidKey)
+          acc_flush<TR, H, RS::K, RS>(lds, A1, g, J0, C0, [](int k) { return RS::off(4, k); });
+        acc_reset(A1, rkey);
+      }
+      // particle data of the next iteration is loaded before the current one
+      // is processed, so its latency overlaps the arithmetic
+      PLoad nx;
+      if (len > 0) nx.load(p, idx0);
+      for (int it = 0; it < kRun; ++it) {
+        const bool valid = it < len;
+        const PLoad cur = nx;
+        if (it + 1 < len) nx.load(p, idx0 + it + 1);
+        double x = 0.0, y = 0.0, z = zmin;
+        float ux = 0.f, uy = 0.f, uz = 0.f, qw = 0.f;
+        if (valid) {
+          x = cur.x;
+          y = cur.y;
+          z = cur.z;
+          ux = cur.ux;
+          uy = cur.uy;
+          uz = (float)cur.uz;
+          qw = cur.w;
+        }
+        const bool cold = __ballot(valid && (ux != 0.f || uy != 0.f || uz != 0.f)) == 0;
+        const float ginv = 1.f / sqrtf(1.f + ux * ux + uy * uy + uz * uz);
+        const float vx = ux * ginv, vy = uy * ginv, vz = uz * ginv;
+        // rho^{n+1} at x^{n+1}, in the run's cell (particles beyond the last
+        // radial node share the last key column and deposit nothing); rho^n
+        // too when the whole wave is at rest
+        if (kRho1J || cold) {
+          const ShapePos s = shape_at(x, y, z, zmin, g);
+          const uint32_t key = pos_key(s, g.nr);
+          float v[RS::K];
+          RS::values(valid && s.i0 < g.nr ? qw : 0.f, s.eith, v);
+          if (kRho1J) acc_add(A1, v, s.fz, s.fr);
+          if (cold) {
+            if (kRhoN) {
+              const uint32_t key0 = valid ? key : An.key;
+              acc_step<TR, H, RS::K, RS>(lds, An, key0, v, s, g, J0, C0, [](int k) { return RS::off(3, k); });
+            }
+            continue;
+          }
+        }
+        // J^{n+1/2} at x^{n+1/2} = x^{n+1} - dt v / 2
+        if (kRho1J) {
+          const ShapePos s = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy,
+                                      z - 0.5 * dt * (double)vz, zmin, g);
+          const uint32_t key = valid ? pos_key(s, g.nr) : (AJ.last_b ? AJ.b.key : AJ.a.key);
+          float v[JS::K];
+          JS::values(valid ? qw : 0.f, vx, vy, vz, s.eith, v);
+          acc2_step<TR, H, JS::K, JS>(lds, AJ, key, v, s, g, J0, C0, [](int k) { return JS::off(k); });
+        }
+        // rho^n at x^n = x^{n+1} - dt v
+        if (kRhoN) {
+          const ShapePos s = shape_at(x - dt * (double)vx, y - dt * (double)vy, z - dt * (double)vz, zmin, g);
+          const uint32_t key = valid ? pos_key(s, g.nr) : An.key;
+          float v[RS::K];
+          RS::values(valid ? qw : 0.f, s.eith, v);
+          acc_step<TR, H, RS::K, RS>(lds, An, key, v, s, g, J0, C0, [](int k) { return RS::off(3, k); });
         }
       }
-      // J^{n+1/2} at x^{n+1/2} = x^{n+1} - dt v / 2
-      {
-        const ShapePos s = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy,
-                                    z - 0.5 * dt * (double)vz, zmin, g);
-        const uint32_t key = valid ? pos_key(s, g.nr) : AJ.key;
-        float v[JS::K];
-        JS::values(valid ? qw : 0.f, vx, vy, vz, s.eith, v);
-        acc_step<TR, H, JS::K, JS>(lds, AJ, key, v, s, g, J0, C0, [](int k) { return JS::off(k); });
-      }
-      // rho^n at x^n = x^{n+1} - dt v
-      {
-        const ShapePos s = shape_at(x - dt * (double)vx, y - dt * (double)vy, z - dt * (double)vz, zmin, g);
-        const uint32_t key = valid ? pos_key(s, g.nr) : An.key;
-        float v[RS::K];
-        RS::values(valid ? qw : 0.f, s.eith, v);
-        acc_step<TR, H, RS::K, RS>(lds, An, key, v, s, g, J0, C0, [](int k) { return RS::off(3, k); });
-      }
     }
+  }   // pieces
+  if (kRho1J) {
+    if (A1.key != kInvalidKey) acc_flush<TR, H, RS::K, RS>(lds, A1, g, J0, C0, [](int k) { return RS::off(4, k); });
+    if (AJ.a.key != kInvalidKey) acc_flush<TR, H, JS::K, JS>(lds, AJ.a, g, J0, C0, [](int k) { return JS::off(k); });
+    if (AJ.b.key != kInvalidKey) acc_flush<TR, H, JS::K, JS>(lds, AJ.b, g, J0, C0, [](int k) { return JS::off(k); });
   }
-  if (A1.key != kInvalidKey) acc_flush<TR, H, RS::K, RS>(lds, A1, g, J0, C0, [](int k) { return RS::off(4, k); });
-  if (An.key != kInvalidKey) acc_flush<TR, H, RS::K, RS>(lds, An, g, J0, C0, [](int k) { return RS::off(3, k); });
-  if (AJ.key != kInvalidKey) acc_flush<TR, H, JS::K, JS>(lds, AJ, g, J0, C0, [](int k) { return JS::off(k); });
+  if (kRhoN && An.key != kInvalidKey) acc_flush<TR, H, RS::K, RS>(lds, An, g, J0, C0, [](int k) { return RS::off(3, k); });
   __syncthreads();
+  constexpr int nr_vals = RhoVals<M>::N;
+  if (MODE == kDepIon) {
+    double* dst = reinterpret_cast<double*>(scratch) + (size_t)b * nr_vals * B::NODES;
+    for (int e = tid; e < nr_vals * B::NODES; e += blockDim.x) {
+      const int k = e / B::NODES, node = e % B::NODES;
+      dst[e] = lds[RS::off(4, k) + node];
+    }
+    return;
+  }
+  if (ionblk && chunk == 0) {
+    // the tile's background, once per tile, in FP64, into the densities this
+    // launch deposits
+    const double* src = ionblk + (size_t)t * nr_vals * B::NODES;
+    for (int e = tid; e < nr_vals * B::NODES; e += blockDim.x) {
+      const int k = e / B::NODES, node = e % B::NODES;
+      const double v = src[e];
+      if (kRhoN) lds[RS::off(3, k) + node] += v;
+      if (kRho1J) lds[RS::off(4, k) + node] += v;
+    }
+    __syncthreads();
+  }
+  if (MODE == kDepEdgeRho) {
+    // only the rho^n part of the tile's first slot (the rest is the carry launch's)
+    float* dst = scratch + (size_t)chunk_start[t] * nacc;
+    for (int e = tid; e < nr_vals * B::NODES; e += blockDim.x) {
+      const int k = e / B::NODES, node = e % B::NODES;
+      dst[RS::off(3, k) + node] = (float)lds[RS::off(3, k) + node];
+    }
+    return;
+  }
   float* dst = scratch + (size_t)b * nacc;
   for (int e = tid; e < nacc; e += blockDim.x) dst[e] = (float)lds[e];
+}
+
+// Set-up of the background blocks: the FP64 rho slots of a tile's work items
+// (the chunks of a dense tile) are summed into the tile's block.
+template <int TR, int H, int M>
+__global__ __launch_bounds__(256) void k_ion_reduce(const int* __restrict__ nchunk, const int* __restrict__ chunk_start,
+                                                    const double* __restrict__ slots, double* __restrict__ ionblk,
+                                                    int ntiles) {
+  constexpr int n = RhoVals<M>::N * Blk<TR, H>::NODES;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)ntiles * n) return;
+  const int t = (int)(i / n), e = (int)(i % n);
+  const double* base = slots + (size_t)chunk_start[t] * n + e;
+  double a = 0.0;
+  for (int c = 0; c < nchunk[t]; ++c) a += base[(size_t)c * n];
+  ionblk[i] = a;
+}
+
+// rho^n of a step that follows a deposit: the previous rho^{n+1} (same
+// particles, same positions), moved one node toward the tail when the window
+// moved in between (the grid node j is then the old node j + 1); the edge
+// columns are overwritten by the edge-tile deposit.
+__global__ __launch_bounds__(256) void k_rho_carry(float2* __restrict__ real, int M, int nr, int nz, int shift) {
+  const int64_t plane = (int64_t)nr * nz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * plane) return;
+  const int64_t m = i / plane, node = i % plane;
+  const int r = (int)(node / nz), j = (int)(node % nz);
+  int js = j + shift;
+  if (js >= nz) js -= nz;
+  const float2* src = real + ((size_t)(kCompJ + 4) * M + m) * plane + (size_t)r * nz;
+  float2* dst = real + ((size_t)(kCompJ + 3) * M + m) * plane + (size_t)r * nz;
+  dst[j] = src[js];
 }
 
 // Chunks of a dense tile: their blocks are summed into the tile's first slot.
@@ -555,13 +718,16 @@ __global__ __launch_bounds__(256) void k_chunk_reduce(const int* __restrict__ nc
 }
 
 // Node-parallel sum of the tile blocks covering the node, then: J-,0 =
-// conj(J+,0), division by the ring volume 2 pi r_i dr dz, immobile background
-// added to both densities.
+// conj(J+,0), division by the ring volume 2 pi r_i dr dz (the immobile
+// background is already in the blocks).
+// rho_n_cols: 0 writes rho^n everywhere; 1 only in the kEdgeCols columns at
+// each end of the window along z (the carried values stay elsewhere); 2 nowhere.
+constexpr int kEdgeColsTail = 2, kEdgeColsHead = 3;   // columns 0..1 and nz-3..nz-1
 template <int TR, int H, int M>
 __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__ chunk_start,
                                                          const float* __restrict__ scratch,
-                                                         float2* __restrict__ real, const float2* __restrict__ bg,
-                                                         Grid g, TileGeom tg) {
+                                                         float2* __restrict__ real, Grid g, TileGeom tg,
+                                                         int rho_n_cols) {
   using B = Blk<TR, H>;
   constexpr int NV = Vals<M>::N;
   constexpr int nacc = NV * B::NODES;
@@ -600,14 +766,6 @@ __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__
   int cs[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) cs[q] = chunk_start[tq[q < nt ? q : 0]];
-  float2 bgv[M][2];
-  if (bg) {
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      bgv[m][0] = bg[(size_t)m * nr * nz + node];
-      bgv[m][1] = bgv[m][0];
-    }
-  }
   float x[4][NV];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -638,13 +796,14 @@ __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__
 #pragma unroll
     for (int sl = 0; sl < 5; ++sl) out[sl][m] = make_float2(acc[b0 + 2 * sl], acc[b0 + 2 * sl + 1]);
   }
+  const bool write_rho_n =
+      rho_n_cols == 0 || (rho_n_cols == 1 && (j < kEdgeColsTail || j >= nz - kEdgeColsHead));
 #pragma unroll
   for (int sl = 0; sl < 5; ++sl)
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      float2 v = cscale(out[sl][m], inv_v);
-      if (bg && sl >= 3) v = cadd(v, bgv[m][sl - 3]);
-      real[dfidx(kCompJ + sl, m, M, nr, nz) + node] = v;
+      if (sl == 3 && !write_rho_n) continue;
+      real[dfidx(kCompJ + sl, m, M, nr, nz) + node] = cscale(out[sl][m], inv_v);
     }
 }
 
@@ -666,29 +825,63 @@ DepositShape deposit_shape(int nz, int nr, int nmodes, int halo, int64_t cap) {
   const int nv = 5 + 10 * (nmodes - 1);
   d.acc_floats2 = ((size_t)nv * bz * br + 1) / 2;     // FP32 scratch slot per work item
   d.lds_bytes = (size_t)nv * bz * br * sizeof(double);
+  d.ion_doubles = (size_t)(2 * nmodes - 1) * bz * br;   // FP64 background block per tile
   return d;
+}
+
+template <class K>
+static bool set_lds_limit(K kernel, size_t bytes) {
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+         hipSuccess;
 }
 
 template <int TR, int H, int M>
 static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chunk_start, float2* scratch,
-                       float2* real, const float2* bg, const Grid& g, const DepositShape& d, DevState* st,
-                       int stages, hipStream_t s) {
+                       float2* real, const double* ionblk, double* ionblk_out, const Grid& g, const DepositShape& d,
+                       DevState* st, int stages, int rho_mode, hipStream_t s) {
   TileGeom tg{d.ntz, d.ntr, d.ntiles, d.tile_max, d.chunk};
   const size_t lds = (size_t)Vals<M>::N * Blk<TR, H>::NODES * sizeof(double);
   if (stages & kDepPlan) {
     hipLaunchKernelGGL((k_tile_totals<TR>), dim3((d.ntiles + 3) / 4), dim3(256), 0, s, offset, g, tg, nchunk);
     hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(1024), 0, s, nchunk, d.ntiles, chunk_start, nchunk + d.ntiles);
+    if (rho_mode != kRhoDeposit) {
+      const int64_t n = (int64_t)g.nmodes * g.nr * g.nz;
+      hipLaunchKernelGGL(k_rho_carry, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, real, g.nmodes, g.nr, g.nz,
+                         rho_mode == kRhoCarryShift ? 1 : 0);
+    }
+  }
+  if (ionblk_out) {   // set-up: FP64 background blocks instead of the grid
+    if (!(stages & kDepTiles)) return;
+    static bool attr_ion = false;
+    if (!attr_ion) {
+      if (!set_lds_limit(k_deposit<TR, H, M, kDepIon>, lds)) return;   // error stays pending for the caller's check
+      attr_ion = true;
+    }
+    hipLaunchKernelGGL((k_deposit<TR, H, M, kDepIon>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
+                       chunk_start, (float*)scratch, (const double*)nullptr, g, tg, st);
+    const int64_t n = (int64_t)d.ntiles * RhoVals<M>::N * Blk<TR, H>::NODES;
+    hipLaunchKernelGGL((k_ion_reduce<TR, H, M>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nchunk,
+                       chunk_start, (const double*)scratch, ionblk_out, d.ntiles);
+    return;
   }
   if (stages & kDepTiles) {
-    static bool attr_set = false;   // dynamic LDS above the default limit
-    if (!attr_set) {
-      if (hipFuncSetAttribute((const void*)k_deposit<TR, H, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds) != hipSuccess)
-        return;   // the error stays pending and is reported by the caller's launch check
-      attr_set = true;
+    static bool attr_set[3] = {false, false, false};   // dynamic LDS above the default limit
+    if (!attr_set[0]) {
+      if (!set_lds_limit(k_deposit<TR, H, M, kDepFull>, lds) || !set_lds_limit(k_deposit<TR, H, M, kDepCarry>, lds) ||
+          !set_lds_limit(k_deposit<TR, H, M, kDepEdgeRho>, lds))
+        return;
+      attr_set[0] = true;
     }
-    hipLaunchKernelGGL((k_deposit<TR, H, M>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk, chunk_start,
-                       (float*)scratch, g, tg, st);
+    if (rho_mode == kRhoDeposit) {
+      hipLaunchKernelGGL((k_deposit<TR, H, M, kDepFull>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
+                         chunk_start, (float*)scratch, ionblk, g, tg, st);
+    } else {
+      hipLaunchKernelGGL((k_deposit<TR, H, M, kDepCarry>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
+                         chunk_start, (float*)scratch, ionblk, g, tg, st);
+      if (rho_mode == kRhoCarryShift)
+        hipLaunchKernelGGL((k_deposit<TR, H, M, kDepEdgeRho>), dim3(2 * d.ntr), dim3(256), lds, s, p, offset, nchunk,
+                           chunk_start, (float*)scratch, ionblk, g, tg, st);
+    }
   }
   if (stages & kDepCombine) {
     constexpr int nacc = Vals<M>::N * Blk<TR, H>::NODES;
@@ -696,28 +889,29 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
     hipLaunchKernelGGL((k_chunk_reduce<TR, H, M>), dim3(items < 1024 ? items : 1024), dim3(256), 0, s, nchunk,
                        nchunk + d.ntiles, chunk_start, (float*)scratch, d.ntiles);
     const int64_t nodes = (int64_t)g.nr * g.nz;
+    const int cols = rho_mode == kRhoDeposit ? 0 : rho_mode == kRhoCarryShift ? 1 : 2;
     hipLaunchKernelGGL((k_deposit_combine<TR, H, M>), dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, s,
-                       chunk_start, (const float*)scratch, real, bg, g, tg);
+                       chunk_start, (const float*)scratch, real, g, tg, cols);
   }
 }
 
 template <int H>
 static void launch_dep_h(const Parts& p, const int* offset, int* nchunk, int* chunk_start, float2* scratch,
-                         float2* real, const float2* bg, const Grid& g, const DepositShape& d, DevState* st,
-                         int stages, hipStream_t s) {
+                         float2* real, const double* ionblk, double* ionblk_out, const Grid& g, const DepositShape& d,
+                         DevState* st, int stages, int rho_mode, hipStream_t s) {
   switch (g.nmodes) {
-    case 1: launch_dep<16, H, 1>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
-    case 2: launch_dep<8, H, 2>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
-    case 3: launch_dep<8, H, 3>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
-    default: launch_dep<8, H, 4>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s); break;
+    case 1: launch_dep<16, H, 1>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
+    case 2: launch_dep<8, H, 2>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
+    case 3: launch_dep<8, H, 3>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
+    default: launch_dep<8, H, 4>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
   }
 }
 
 void launch_deposit(const Parts& p, const int* offset, const DepositShape& d, int* nchunk, int* chunk_start,
-                    float2* scratch, float2* real, const float2* bg, const Grid& g, DevState* st, int stages,
-                    hipStream_t s) {
-  if (d.halo == 1) launch_dep_h<1>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s);
-  else launch_dep_h<2>(p, offset, nchunk, chunk_start, scratch, real, bg, g, d, st, stages, s);
+                    float2* scratch, float2* real, const double* ionblk, double* ionblk_out, const Grid& g,
+                    DevState* st, int stages, int rho_mode, hipStream_t s) {
+  if (d.halo == 1) launch_dep_h<1>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s);
+  else launch_dep_h<2>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s);
 }
 
 }  // namespace pic

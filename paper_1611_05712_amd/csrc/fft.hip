@@ -99,7 +99,8 @@ __device__ __forceinline__ void load_tw8(const float2* __restrict__ tw, int N, i
 // j = t + jj tpr.  Twiddles apply for Ns > 1 (radix-8 passes only).
 template <int R, bool INV, int VPT, int JJ8>
 __device__ __forceinline__ void pass_compute(const float2* src, int N, int Ns, int t, int tpr,
-                                             const float2 (&w)[JJ8][7], float2 (&v)[VPT]) {
+                                             const float2 (&w)[JJ8][7], float2 (&v)[VPT],
+                                             const float2* minus = nullptr) {
   const int NR = N / R;
   constexpr int JJ = VPT / R;
 #pragma unroll
@@ -109,6 +110,10 @@ __device__ __forceinline__ void pass_compute(const float2* src, int N, int Ns, i
       float2* u = v + jj * R;
 #pragma unroll
       for (int r = 0; r < R; ++r) u[r] = src[j + r * NR];
+      if (minus) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = csub(u[r], minus[j + r * NR]);
+      }
       if constexpr (R == 8) {
         if (Ns > 1) {
 #pragma unroll
@@ -162,11 +167,11 @@ __device__ __forceinline__ void pass_store(float2* dst, int N, int Ns, int t, in
 }
 
 template <bool INV, int R0, int VPT>
-__device__ __forceinline__ void first_pass(const float2* gin, float2* buf, float2* gout, int N, int t, int tpr,
-                                           bool active, bool last, const FftOut& o, const float2 (&w)[VPT / 8][7],
-                                           float2 (&v)[VPT]) {
+__device__ __forceinline__ void first_pass(const float2* gin, const float2* gminus, float2* buf, float2* gout, int N,
+                                           int t, int tpr, bool active, bool last, const FftOut& o,
+                                           const float2 (&w)[VPT / 8][7], float2 (&v)[VPT]) {
   if (active) {
-    pass_compute<R0, INV, VPT, VPT / 8>(gin, N, 1, t, tpr, w, v);
+    pass_compute<R0, INV, VPT, VPT / 8>(gin, N, 1, t, tpr, w, v, gminus);
     if (last) pass_store<R0, true, VPT>(gout, N, 1, t, tpr, o, v);
     else pass_store<R0, false, VPT>(buf, N, 1, t, tpr, o, v);
   }
@@ -177,11 +182,13 @@ __device__ __forceinline__ void first_pass(const float2* gin, float2* buf, float
 // workgroup, then writes its outputs in place (16 KB of LDS per 2048-point
 // row).  The twiddles of pass p + 1 are requested before pass p starts, so
 // their latency hides behind that pass.  VPT: complex values per thread and
-// pass (8 up to 2048 points, 16 at 4096).
+// pass (8 up to 2048 points, 16 at 4096).  Rows [diff_lo, diff_hi) transform
+// the difference in[row + diff_off] - in[row] instead of in[row].
 template <bool INV, int VPT>
 __global__ __launch_bounds__(256) void k_fft(const float2* __restrict__ in, float2* __restrict__ out,
                                              const float2* __restrict__ tw, int N, int logN, int rows_per_wg,
-                                             int64_t rows, int shift, float2* tail) {
+                                             int64_t rows, int shift, float2* tail, int64_t diff_lo,
+                                             int64_t diff_hi, int64_t diff_off) {
   constexpr int JJ8 = VPT / 8;
   extern __shared__ float2 lds[];
   const int tpr = blockDim.x / rows_per_wg;
@@ -191,6 +198,11 @@ __global__ __launch_bounds__(256) void k_fft(const float2* __restrict__ in, floa
   const bool active = row < rows;
   float2* buf = lds + (size_t)rloc * N;
   const float2* gin = in + row * N;
+  const float2* gminus = nullptr;
+  if (row >= diff_lo && row < diff_hi) {
+    gminus = gin;
+    gin = in + (row + diff_off) * N;
+  }
   float2* gout = out + row * N;
   FftOut o;
   o.shift = INV && shift;
@@ -206,9 +218,9 @@ __global__ __launch_bounds__(256) void k_fft(const float2* __restrict__ in, floa
   if (npass > 1 && active) load_tw8<JJ8>(tw, N, R0, t, tpr, w);
   {
     const bool last = npass == 1;
-    if (R0 == 2) first_pass<INV, 2, VPT>(gin, buf, gout, N, t, tpr, active, last, o, w, v);
-    else if (R0 == 4) first_pass<INV, 4, VPT>(gin, buf, gout, N, t, tpr, active, last, o, w, v);
-    else first_pass<INV, 8, VPT>(gin, buf, gout, N, t, tpr, active, last, o, w, v);
+    if (R0 == 2) first_pass<INV, 2, VPT>(gin, gminus, buf, gout, N, t, tpr, active, last, o, w, v);
+    else if (R0 == 4) first_pass<INV, 4, VPT>(gin, gminus, buf, gout, N, t, tpr, active, last, o, w, v);
+    else first_pass<INV, 8, VPT>(gin, gminus, buf, gout, N, t, tpr, active, last, o, w, v);
   }
   __syncthreads();
   int Ns = R0;
@@ -241,7 +253,7 @@ void fft_config(int nz, int& rows_per_wg, size_t& lds) {
 
 template <bool INV>
 static void launch_fft_dir(const float2* in, float2* out, const float2* tw, int nz, int64_t rows, bool shift,
-                           float2* tail, hipStream_t s) {
+                           float2* tail, int64_t diff_lo, int64_t diff_hi, int64_t diff_off, hipStream_t s) {
   int rpw;
   size_t lds;
   fft_config(nz, rpw, lds);
@@ -249,16 +261,16 @@ static void launch_fft_dir(const float2* in, float2* out, const float2* tw, int 
   const int logN = ilog2(nz);
   if (nz > 2048)
     hipLaunchKernelGGL((k_fft<INV, 16>), dim3((unsigned)nb), dim3(256), lds, s, in, out, tw, nz, logN, rpw, rows,
-                       shift ? 1 : 0, tail);
+                       shift ? 1 : 0, tail, diff_lo, diff_hi, diff_off);
   else
     hipLaunchKernelGGL((k_fft<INV, 8>), dim3((unsigned)nb), dim3(256), lds, s, in, out, tw, nz, logN, rpw, rows,
-                       shift ? 1 : 0, tail);
+                       shift ? 1 : 0, tail, diff_lo, diff_hi, diff_off);
 }
 
 void launch_fft(const float2* in, float2* out, const float2* tw, int nz, int64_t rows, bool inverse, bool shift,
-                float2* tail, hipStream_t s) {
-  if (inverse) launch_fft_dir<true>(in, out, tw, nz, rows, shift, tail, s);
-  else launch_fft_dir<false>(in, out, tw, nz, rows, false, tail, s);
+                float2* tail, hipStream_t s, int64_t diff_lo, int64_t diff_hi, int64_t diff_off) {
+  if (inverse) launch_fft_dir<true>(in, out, tw, nz, rows, shift, tail, 0, 0, 0, s);
+  else launch_fft_dir<false>(in, out, tw, nz, rows, false, tail, diff_lo, diff_hi, diff_off, s);
 }
 
 }  // namespace pic

@@ -52,25 +52,38 @@ struct DepositShape {
   int halo;             // cells a particle can move per step (1 or 2)
   int max_items;        // workgroups launched (upper bound of the work list)
   size_t acc_floats2;   // FP32 scratch slot per work item, in float2 units (values x block nodes)
-  size_t lds_bytes;     // FP64 LDS block of one workgroup
+  size_t lds_bytes;     // LDS of one workgroup: FP64 node block + particle staging
   int chunk;            // particles per chunk of a dense tile (2048 .. 8192, tunable)
   int tile_max;         // tiles above this many particles are chunked (3 x chunk)
+  size_t ion_doubles;   // FP64 immobile-background block per tile (rho values x block nodes)
 };
 DepositShape deposit_shape(int nz, int nr, int nmodes, int halo, int64_t cap);
 // stages of the deposit: work-list planning, tile accumulation, node combine.
 // nchunk holds 2 ntiles + 1 ints: chunks per tile, then the list of tiles with
 // more than one chunk and its length; chunk_start holds ntiles + 1.
 constexpr int kDepPlan = 1, kDepTiles = 2, kDepCombine = 4, kDepAll = 7;
+// ionblk: the per-tile FP64 background blocks added to both densities (null:
+// none).  ionblk_out non-null: set-up pass that deposits the particles (the
+// immobile background) into those blocks instead of the grid.
+// rho_mode: how rho^n is formed.  kRhoDeposit: deposited at x^n like the
+// other sources.  After a deposit of the same particles, rho^n is the previous
+// rho^{n+1}: kRhoCarry copies it (window at rest), kRhoCarryShift copies it one
+// node toward the tail (the window moved by one cell) and re-deposits rho^n in
+// the edge tiles at both ends of the window, where particles left and the new
+// head column entered.
+constexpr int kRhoDeposit = 0, kRhoCarry = 1, kRhoCarryShift = 2;
 void launch_deposit(const Parts& p, const int* offset, const DepositShape& d, int* nchunk, int* chunk_start,
-                    float2* scratch, float2* real, const float2* bg, const Grid& g, DevState* st, int stages,
-                    hipStream_t s);
+                    float2* scratch, float2* real, const double* ionblk, double* ionblk_out, const Grid& g,
+                    DevState* st, int stages, int rho_mode, hipStream_t s);
 void launch_inject(const Parts& p, DevState* st, const Grid& g, const InjectTable& tab, int cap, hipStream_t s);
 void launch_uniform_check(const float2* rho, int rows, int nz, unsigned int* out, hipStream_t s);
 
 // fields
 void fft_config(int nz, int& rows_per_wg, size_t& lds);
+// Forward transforms of rows [diff_lo, diff_hi) take in[row + diff_off] - in[row]
+// as their input (rho^{n+1} - rho^n without an intermediate array).
 void launch_fft(const float2* in, float2* out, const float2* tw, int nz, int64_t rows, bool inverse, bool shift,
-                float2* tail, hipStream_t s);
+                float2* tail, hipStream_t s, int64_t diff_lo = 0, int64_t diff_hi = 0, int64_t diff_off = 0);
 int gemm_tile_bm(int n, int pref_bm);
 void launch_dht_gemm(const float* const* at, const float* const* x, float* const* y, int batch, int n, int ncols,
                      int prec, int pref_bm, hipStream_t s);

@@ -1,16 +1,16 @@
 // Surrogate network: forward, backward and Adam kernels of a small GELU
 // multilayer perceptron, plus the C interface of include/mlp.h.
 //
-// Every matrix product of the network (forward layer, gradient of a layer's
-// input, gradient of its weights) runs through one LDS-tiled kernel: a
-// 256-thread workgroup computes a 32 x 32 output tile, staging 32-deep slices
-// of both operands in LDS as float32, each thread accumulating a 2 x 2 block in
-// float32.  Operands are read through strides, so the transposes of the
-// backward pass cost nothing, and as float32 or bfloat16 (the BF16 mode).
-// The bias, GELU and GELU-derivative steps are fused into the product's
-// epilogue.  The network is small (batch 256, width 128), so each launch is a
-// few microseconds and the training loop is launch bound; the products are
-// not worth matrix-core tiles at these sizes.
+// Matrix products (forward layer, gradient of a layer's input, gradient of
+// its weights), C(m, n) = sum_k A(m, k) B(k, n) with operands read through
+// strides (the transposes of the backward pass cost nothing):
+//   * both operands bfloat16 (the BF16 mode's hidden layers and gradients):
+//     matrix cores, v_mfma_f32_32x32x16_bf16 with FP32 accumulation; each
+//     wavefront computes one 32 x 32 output tile, four per workgroup;
+//   * otherwise (FP32 mode, and the layer that reads the FP32 input
+//     features): a 256-thread workgroup per 32 x 32 output tile staging
+//     32-deep slices of both operands in LDS, each thread accumulating 2 x 2.
+// The bias, GELU and GELU-derivative steps are fused into the epilogue.
 #include <cmath>
 #include <type_traits>
 #include <vector>
@@ -111,6 +111,66 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const TA* __restrict__ a, int6
       } else {
         st(out, o, c);
       }
+    }
+  }
+}
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// 8 consecutive-k bfloat16 values of an operand, zero outside [0, M) x [0, K)
+__device__ __forceinline__ bf16x8 load8_bf16(const uint16_t* __restrict__ p, int64_t s_row, int64_t s_k, int row,
+                                             int k0, int nrow, int nk) {
+  bf16x8 v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int k = k0 + e;
+    const uint16_t h = (row < nrow && k < nk) ? p[(size_t)((int64_t)row * s_row + (int64_t)k * s_k)] : (uint16_t)0;
+    v[e] = __builtin_bit_cast(__bf16, h);
+  }
+  return v;
+}
+
+// C(m, n) = sum_k A(m, k) B(k, n), A and B bfloat16, on the matrix cores.
+// Lane l of a wavefront holds rows / columns (l & 31) and k = 8 (l >> 5) + 0..7
+// of each 16-deep step; accumulator element r is row 8 (r >> 2) + 4 (l >> 5)
+// + (r & 3), column (l & 31).
+template <typename TO, int EPI>
+__global__ __launch_bounds__(256) void k_mlp_gemm_mfma(const uint16_t* __restrict__ a, int64_t sam, int64_t sak,
+                                                       const uint16_t* __restrict__ b, int64_t sbk, int64_t sbn, int M,
+                                                       int N, int K, const float* __restrict__ bias,
+                                                       const float* __restrict__ zin, float* __restrict__ zout,
+                                                       TO* __restrict__ out, int64_t ldo) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32, n0 = blockIdx.x * 64 + (wave & 1) * 32;
+  if (m0 >= M || n0 >= N) return;   // uniform per wavefront
+  const int kb = 8 * (lane >> 5);
+  floatx16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x8 av = load8_bf16(a, sam, sak, m0 + (lane & 31), k0 + kb, M, K);
+    const bf16x8 bv = load8_bf16(b, sbn, sbk, n0 + (lane & 31), k0 + kb, N, K);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+  }
+  const int n = n0 + (lane & 31);
+  if (n >= N) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (m >= M) continue;
+    const size_t o = (size_t)m * ldo + n;
+    const float c = acc[r];
+    if (EPI == kEpiBiasGelu) {
+      const float z = c + bias[n];
+      zout[o] = z;
+      st(out, o, gelu(z));
+    } else if (EPI == kEpiBias) {
+      zout[o] = c + bias[n];
+    } else if (EPI == kEpiGeluGrad) {
+      st(out, o, c * gelu_d(zin[o]));
+    } else {
+      st(out, o, c);
     }
   }
 }
@@ -295,9 +355,15 @@ size_t carve_mlp(pic_mlp* x, char* base, const pic_mlp_config* c) {
 template <typename TA, typename TB, typename TO, int EPI>
 void gemm(hipStream_t s, const TA* a, int64_t sam, int64_t sak, const TB* b, int64_t sbk, int64_t sbn, int M, int N,
           int K, const float* bias, const float* zin, float* zout, TO* out, int64_t ldo) {
-  dim3 grid(nblk(N, 32), nblk(M, 32));
-  hipLaunchKernelGGL((k_mlp_gemm<TA, TB, TO, EPI>), grid, dim3(256), 0, s, a, sam, sak, b, sbk, sbn, M, N, K, bias,
-                     zin, zout, out, ldo);
+  if constexpr (std::is_same<TA, uint16_t>::value && std::is_same<TB, uint16_t>::value) {
+    dim3 grid(nblk(N, 64), nblk(M, 64));
+    hipLaunchKernelGGL((k_mlp_gemm_mfma<TO, EPI>), grid, dim3(256), 0, s, a, sam, sak, b, sbk, sbn, M, N, K, bias,
+                       zin, zout, out, ldo);
+  } else {
+    dim3 grid(nblk(N, 32), nblk(M, 32));
+    hipLaunchKernelGGL((k_mlp_gemm<TA, TB, TO, EPI>), grid, dim3(256), 0, s, a, sam, sak, b, sbk, sbn, M, N, K, bias,
+                       zin, zout, out, ldo);
+  }
 }
 
 // Forward pass over n rows of x (float32); returns the output array z[L-1].

@@ -12,7 +12,12 @@
 //   div V     = k_perp (V+ - V-) + i [k_z] Vz
 // Current correction: J += grad F, F = (div J + (rho^{n+1} - rho^n)/dt) / k^2.
 // The coefficients are evaluated in FP64 (C, S, and the cancellation-prone
-// S/(k dt) - 1 near k -> 0) and rounded once to float32.
+// 1 - C and C - S/(k dt) near k -> 0) and rounded once to float32.
+//
+// The rho^n slot holds d = rho^{n+1} - rho^n, transformed as such: F takes d
+// directly, and the charge term is written
+//   (S/(k dt) - 1) rho^{n+1} + (C - S/(k dt)) rho^n = (C - 1) rho^{n+1} - (C - S/(k dt)) d,
+// so no difference of two separately rounded transforms enters the update.
 //
 // A moving window shifts the real-space fields one cell toward the tail and
 // zeroes the head column.  On the spectral state that is
@@ -25,7 +30,7 @@
 namespace pic {
 
 struct Coef {
-  float C, Sk, omc, r1, r0, ik2;
+  float C, Sk, omc, r0, ik2;
 };
 
 __device__ __forceinline__ Coef make_coef(double kp, double kz, double dt) {
@@ -39,7 +44,6 @@ __device__ __forceinline__ Coef make_coef(double kp, double kz, double dt) {
   o.C = (float)c;
   o.Sk = (float)(s / k);
   o.omc = (float)((1.0 - c) / k2);
-  o.r1 = (float)((sx - 1.0) / k2);
   o.r0 = (float)((c - sx) / k2);
   o.ik2 = (float)(1.0 / k2);
   return o;
@@ -69,8 +73,8 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
       B[m][c] = spec[((size_t)(3 + c) * M + m) * plane + cell];
       J[m][c] = spec[((size_t)(6 + c) * M + m) * plane + cell];
     }
-    r0[m] = spec[((size_t)9 * M + m) * plane + cell];
-    r1[m] = spec[((size_t)10 * M + m) * plane + cell];
+    r0[m] = spec[((size_t)kCompRho0 * M + m) * plane + cell];      // rho^{n+1} - rho^n
+    r1[m] = spec[((size_t)(kCompRho0 + 1) * M + m) * plane + cell];
   }
   float2 th[M][6];
   if (apply_shift) {
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
       Bm[c] = B[m][c];
       Jm[c] = J[m][c];
     }
-    float2 q0 = r0[m], q1 = r1[m];
+    float2 dq = r0[m], q1 = r1[m];
     if (filter) {
       // `filter` binomial (1/4, 1/2, 1/4) passes along z and along r, in spectral form
       const double cz = cos(0.5 * kz_grid[iz] * dz), cr = cos(0.5 * kpd * dr);
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
       const float fs = (float)fp;
 #pragma unroll
       for (int c = 0; c < 3; ++c) Jm[c] = cscale(Jm[c], fs);
-      q0 = cscale(q0, fs);
+      dq = cscale(dq, fs);
       q1 = cscale(q1, fs);
     }
     if (apply_shift) {
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
     }
     if (correct) {
       float2 dvj = cadd(cscale(csub(Jm[0], Jm[1]), kp), cmuli(cscale(Jm[2], kz)));
-      float2 F = cscale(cadd(dvj, cscale(csub(q1, q0), idt)), co.ik2);
+      float2 F = cscale(cadd(dvj, cscale(dq, idt)), co.ik2);
       Jm[0] = cadd(Jm[0], cscale(F, -0.5f * kp));
       Jm[1] = cadd(Jm[1], cscale(F, 0.5f * kp));
       Jm[2] = cadd(Jm[2], cmuli(cscale(F, kz)));
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(256) void k_psatd(float2* __restrict__ spec, const 
       cJ[1] = csub(cscale(Jm[1], -kz), cmuli(cscale(Jm[2], hk)));
       cJ[2] = cmuli(cscale(cadd(Jm[0], Jm[1]), kp));
     }
-    const float2 gs = cadd(cscale(q1, co.r1), cscale(q0, co.r0));
+    const float2 gs = csub(cscale(q1, -co.omc), cscale(dq, co.r0));
     const float2 g[3] = {cscale(gs, -0.5f * kp), cscale(gs, 0.5f * kp), cmuli(cscale(gs, kz))};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

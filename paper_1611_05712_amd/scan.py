@@ -93,15 +93,17 @@ def witness_state(sim: Simulation):
 
 
 def ncr_error_scan(n_tuples: int, steps: int, seed: int = 1, group: int = 4, log=None,
-                   device: str = "cuda:0") -> Dict[str, object]:
+                   device: str = "cuda:0", first: int = 0) -> Dict[str, object]:
     """Runs every physical tuple of a seeded scan at every stencil order
     (8 ... 64 and infinite), `group` tuples at a time in one batch, and returns
     per tuple the witness state of every run and, per finite order, the
     paper's Err_sigma_gamma (Eq. (11)) and Err_eps (Eq. (12), on eps_n,x)
-    against the infinite-order twin."""
+    against the infinite-order twin.  `first` skips the first tuples of the
+    seeded sequence (tuple k is the same set-up whatever the range), so a long
+    scan can be run in parts and merged."""
     import numpy as np
     from workloads import scan_instances, scan_workload
-    insts = [i for i in scan_instances(n_tuples=n_tuples, seed=seed, extra=0)]
+    insts = [i for i in scan_instances(n_tuples=first + n_tuples, seed=seed, extra=0) if i.tuple_index >= first]
     by_tuple: Dict[int, list] = {}
     for i in insts:
         by_tuple.setdefault(i.tuple_index, []).append(i)
@@ -152,9 +154,20 @@ if __name__ == "__main__":
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--group", type=int, default=4)
+    ap.add_argument("--first", type=int, default=0, help="first tuple index of this part of the scan")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--merge", nargs="*", default=None, metavar="PART",
+                    help="instead of running: merge scan parts (same seed and steps) into --out")
     a = ap.parse_args()
-    res = ncr_error_scan(a.tuples, a.steps, a.seed, a.group, log=lambda m: print(m, file=sys.stderr, flush=True))
+    if a.merge:
+        parts = [json.load(open(f)) for f in a.merge]
+        assert len({(q["seed"], q["steps"]) for q in parts}) == 1, "parts of different scans"
+        tuples = sorted((t for q in parts for t in q["tuples"]), key=lambda t: t["tuple"])
+        assert len({t["tuple"] for t in tuples}) == len(tuples), "overlapping parts"
+        res = dict(parts[0], tuples=tuples, batched_s=sum(q["batched_s"] for q in parts))
+    else:
+        res = ncr_error_scan(a.tuples, a.steps, a.seed, a.group, log=lambda m: print(m, file=sys.stderr, flush=True),
+                             first=a.first)
     with open(a.out, "w") as f:
         json.dump(res, f, indent=1)
     print(f"wrote {a.out}: {len(res['tuples'])} tuples", file=sys.stderr)

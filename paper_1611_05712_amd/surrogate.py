@@ -148,6 +148,45 @@ def select_with_fallback(pick: int, judge: Callable[[int], Tuple[float, float]],
     return 0, ran
 
 
+def settle_cost(ran: Sequence[int]) -> int:
+    """Simulations needed to settle a set-up's order: the infinite-order run
+    (the twin every finite order is judged against, or, when the pick is
+    infinite, the production run itself) plus every finite order simulated."""
+    return 1 + len(ran)
+
+
+def majority_order(scan: Dict[str, object], tuple_ids: Sequence[int], orders=ORDERS) -> int:
+    """The most frequent required order over the given set-ups (ties: the
+    lower order); the no-network predictor that always picks it."""
+    req = [required_order(t, orders=orders) for t in scan["tuples"] if t["tuple"] in set(tuple_ids)]
+    counts = {p: req.count(p) for p in tuple(orders) + (0,)}
+    rank = {p: i for i, p in enumerate(tuple(orders) + (0,))}
+    return max(counts, key=lambda p: (counts[p], -rank[p]))
+
+
+def compare_pickers(scan: Dict[str, object], held_ids: Sequence[int], pickers: Dict[str, Callable],
+                    orders=ORDERS) -> Dict[str, Dict[str, int]]:
+    """For each picker (set-up record -> order, 0 = infinite): over the held-out
+    set-ups, the simulations needed with the judge's fallback (settle_cost),
+    how often the accepted order is the scan's answer, and how often it is
+    higher.  The scan itself needs every finite order plus the twin."""
+    recs = {t["tuple"]: t for t in scan["tuples"]}
+    rank = {p: i for i, p in enumerate(tuple(orders) + (0,))}
+    out = {name: {"runs": 0, "exact": 0, "over": 0} for name in pickers}
+    out["scan"] = {"runs": 0, "exact": 0, "over": 0}
+    for k in held_ids:
+        t = recs[k]
+        want = required_order(t, orders=orders)
+        out["scan"]["runs"] += len(orders) + 1
+        out["scan"]["exact"] += 1
+        for name, pick_fn in pickers.items():
+            got, ran = select_with_fallback(pick_fn(t), table_judge(t), orders=orders)
+            out[name]["runs"] += settle_cost(ran)
+            out[name]["exact"] += int(got == want)
+            out[name]["over"] += int(rank[got] > rank[want])
+    return out
+
+
 def table_judge(t: Dict[str, object]) -> Callable[[int], Tuple[float, float]]:
     """Judge from a scan record (the errors its plain simulations measured)."""
     def judge(p: int):

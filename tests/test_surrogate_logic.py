@@ -46,3 +46,33 @@ def test_fallback_ends_at_infinite_order():
     t = _record({p: (0.5, 0.0) for p in S.ORDERS})
     got, r = S.select_with_fallback(48, S.table_judge(t))
     assert got == 0 and r == [48, 64]
+
+
+def test_settle_cost_counts_the_infinite_order_run():
+    # a pick of infinity costs its one production run; a finite pick costs the
+    # twin plus every order the fallback climbed through
+    assert S.settle_cost([]) == 1
+    assert S.settle_cost([16, 24]) == 3
+
+
+def test_compare_pickers_against_no_network_baselines():
+    recs = [_record({8: (0.2, 0.0), 16: (0.01, 0.0), 24: (0.0, 0.0), 32: (0.0, 0.0), 48: (0.0, 0.0),
+                     64: (0.0, 0.0)}),
+            _record({p: (0.5, 0.0) for p in S.ORDERS}),
+            _record({p: (0.0, 0.0) for p in S.ORDERS})]
+    for k, r in enumerate(recs):
+        r["tuple"] = k
+    scan = {"tuples": recs}
+    want = [16, 0, 8]
+    assert [S.required_order(r) for r in recs] == want
+    assert S.majority_order(scan, [0, 1, 2]) == 8      # all counts 1: the lowest order wins the tie
+    oracle_pick = {0: 16, 1: 0, 2: 8}
+    res = S.compare_pickers(scan, [0, 1, 2], {
+        "perfect": lambda t: oracle_pick[t["tuple"]],
+        "infinite": lambda t: 0,
+        "climb": lambda t: S.ORDERS[0]})
+    assert res["scan"] == {"runs": 21, "exact": 3, "over": 0}
+    assert res["perfect"] == {"runs": 2 + 1 + 2, "exact": 3, "over": 0}
+    assert res["infinite"] == {"runs": 3, "exact": 1, "over": 2}
+    # climbing from the lowest order always finds the answer, at 3 + 7 + 2 runs
+    assert res["climb"] == {"runs": 3 + 7 + 2, "exact": 3, "over": 0}
