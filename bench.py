@@ -224,6 +224,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1500)
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--hankel-prec", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
+    ap.add_argument("--damp-cells", type=int, default=0, metavar="N",
+                    help="variant: absorbing layers of N cells at both z ends (not the headline line)")
+    ap.add_argument("--galilean", action="store_true",
+                    help="variant: Galilean field update in coordinates moving with the window (not the headline line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="time eager steps instead of replays of the captured two-step HIP graph")
@@ -261,6 +265,8 @@ def main():
 
     prec = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}[args.hankel_prec]
     wl = preset(args.workload)
+    wl.damp_cells = args.damp_cells
+    wl.galilean = args.galilean
     sim = Simulation.from_workload(wl, hankel_prec=prec, device="cuda:0")
     t0 = time.perf_counter()
     (sim.step if args.eager else sim.step_graph)(args.warmup)
@@ -325,7 +331,8 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "mobile_particles": int(n_part), "cells_per_mode": wl.nz * wl.nr,
                    "modes": wl.n_modes, "order": wl.order,
-                   "hankel_prec": args.hankel_prec, "positions": "f64",
+                   "hankel_prec": args.hankel_prec, "positions": "f64", "damp_cells": args.damp_cells,
+                   "galilean": args.galilean,
                    "stepping": "eager" if args.eager else "hip graph, two steps per replay"},
         "field_cell_updates_per_s": cells * args.steps / (spectral_ms / 1e3) if spectral_ms else None,
         "roofline": roofline,

@@ -54,7 +54,9 @@ typedef enum {
   PIC_ENOSPC = -2,    /* workspace too small, or particle capacity exceeded */
   PIC_EHIP = -3,      /* HIP runtime error (launch or asynchronous fault) */
   PIC_ESTATE = -4,    /* call out of order (see the step order below) */
-  PIC_ENUMERIC = -5   /* NaN or Inf found by pic_diagnostics */
+  PIC_ENUMERIC = -5   /* NaN or Inf found by pic_diagnostics, or produced by a split-precision
+                         Hankel product (an operand beyond the range of its halves: FP16
+                         65504), reported by the next synchronizing call */
 } pic_status;
 
 /* Radial wavenumber grid of the discrete Hankel transform.  In mode m the
@@ -109,6 +111,25 @@ typedef struct {
                                  [cos^2(k_z dz / 2) cos^2(k_perp dr / 2)]^n (zero at the z Nyquist
                                  wavenumber, where a beam at dt = dz / c drives the numerical
                                  Cherenkov instability of the infinite-order solver) */
+  int32_t damp_cells;         /* absorbing layers at the z ends of the grid: 0 = none (default);
+                                 N in 1..nz/4: after every step the real-space E and B at the N
+                                 nodes nearest each z end are multiplied by sin^2(pi s / (2 N)),
+                                 s = 0..N-1 the node's distance in cells from the end node (the
+                                 end node is zeroed), and the next step transforms E and B from
+                                 real space again, so the field state is the damped one.  Keeps
+                                 what leaves the grid at one end from re-entering at the other
+                                 through the periodic z transform */
+  int32_t galilean;           /* 1 (needs moving_window): Galilean PSATD (the scheme the paper
+                                 names as intrinsically stable for drifting plasmas, Sec. "Finite
+                                 order pseudo-spectral solvers"): the fields live in coordinates
+                                 moving with the window, v = dz / dt, where Maxwell's equations
+                                 gain the advection term i [k_z] v F; the update is their exact
+                                 solution with J constant over the step, the current correction
+                                 enforces the moving-frame continuity equation, rho^{n+1} and J
+                                 are carried onto the grids of t^{n+1} and t^{n+1/2} (exact
+                                 periodic one- and half-node moves; the half move is zero at the
+                                 z Nyquist wavenumber) and E, B are not shifted by the window
+                                 move.  0 (default): the lab-frame update of Eqs. (1a)-(1b) */
 } pic_config;
 
 typedef struct {
@@ -311,7 +332,8 @@ typedef enum {
   PIC_T_PSATD = 5,       /* window shift + current correction + PSATD update */
   PIC_T_DHT_INV = 6,     /* inverse Hankel-transform products of E, B */
   PIC_T_FFT_INV = 7,     /* inverse z-FFT of E, B (+ window shift) */
-  PIC_T_WINDOW = 8,      /* departed-column transform, window advance, injection */
+  PIC_T_WINDOW = 8,      /* departed-column transform, window advance, injection,
+                            absorbing layers */
   PIC_T_SCAN = 9,        /* exclusive scan of the per-cell particle counts */
   PIC_T_DEP_PLAN = 10,   /* deposit work list: particles per tile, chunk offsets */
   PIC_T_DEP_COMBINE = 11,/* node-parallel sum of the tile blocks into the grid */
@@ -350,10 +372,38 @@ int pic_set_tuning(pic_ctx* ctx, const pic_tuning* t);
  * otherwise).  Asynchronous like pic_step; same results to rounding. */
 int pic_step_graph(pic_ctx* ctx, int n);
 
-/* n steps of each of n_ctx independent contexts (distinct streams), issued two
- * steps at a time in round-robin so that the instances overlap on the GPU;
- * each context advances as with pic_step_graph.  Errors as pic_step_graph for
- * the first failing context; contexts before it have advanced. */
+/* A batch of independent contexts (parameter scans: many instances with
+ * different grids, orders and beams, Sec. "Accurate modeling of plasma
+ * accelerators in finite order PSATD") advanced by ONE HIP graph: two steps of
+ * every context, each on the context's own stream, forked from and joined
+ * into the batch's lead stream, so that one graph launch advances the whole
+ * batch by two steps and the GPU overlaps the instances' kernels.
+ *
+ * pic_batch_create: ctxs holds n_ctx >= 1 distinct contexts of the current
+ * device, each with its own non-null stream; the batch keeps the pointers
+ * (the contexts must outlive it) and owns a lead stream and events.  Nothing
+ * is captured yet.  Errors: PIC_EINVAL (null or repeated context, legacy
+ * stream), PIC_EHIP.
+ *
+ * pic_batch_run: n steps of every context.  A first step after pic_init or
+ * pic_set_field of any context runs eagerly on every context; the graph is
+ * captured at the first run and again when a context's tunables or pending
+ * window shift differ from those it was captured with; an odd last step runs
+ * eagerly.  Each context's later work on its own stream is ordered after the
+ * replays.  Asynchronous.  Every context must be at the start of a step with
+ * timing off.  Same results as pic_step to rounding.  Errors: PIC_ESTATE,
+ * PIC_EINVAL, PIC_EHIP (steps already enqueued stay enqueued).
+ *
+ * pic_batch_free: waits for the batch's replays, then releases the graph,
+ * events and lead stream (not the contexts).  Errors: PIC_EINVAL, PIC_EHIP. */
+typedef struct pic_batch pic_batch;
+int pic_batch_create(pic_ctx* const* ctxs, int n_ctx, pic_batch** out);
+int pic_batch_run(pic_batch* batch, int n);
+int pic_batch_free(pic_batch* batch);
+
+/* n steps of each of n_ctx independent contexts: pic_batch_create, then
+ * pic_batch_run(n), then pic_batch_free (so it returns once the replays are
+ * done).  n_ctx = 0 or n = 0 does nothing.  Errors as those calls. */
 int pic_batch_step(pic_ctx* const* ctxs, int n_ctx, int n);
 
 /* Autotuner: for every supported (gemm_tile_m, deposit_chunk) pair, runs two

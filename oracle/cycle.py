@@ -16,7 +16,18 @@ real-space fields the particles see.  Per step n:
      shift one cell toward the tail and the head column is zeroed; the
      spectral state gets the same shift, Fh <- exp(i k_z dz) (Fh - Hankel
      transform of the departed tail column); particles behind the new zmin
-     are removed and a fresh lattice column is injected at the head.
+     are removed and a fresh lattice column is injected at the head;
+  7. absorbing layers (when enabled, `damp_cells` = N > 0): the real-space
+     E, B at the N nodes nearest each z end are multiplied by
+     sin^2(pi s / (2N)), s the node's distance in cells from the end node,
+     and the damped real-space fields become the state (forward transformed
+     at the next spectral push).
+Galilean variant (`galilean`, with the moving window): the fields live in
+coordinates moving with the grid (v = dz/dt, one cell per step); at step 4
+rho^{n+1} is moved onto the grid at t^{n+1} (one cell) and J onto the grid at
+t^{n+1/2} (half a cell) in spectral form, the current correction and the
+update are the Galilean ones (spectral.psatd_push_galilean), and at step 6 the
+fields are not shifted (they already are on the moved grid).
 
 Fields written in real space with set_fields() become the state at the next
 spectral push (they are forward transformed then).
@@ -51,6 +62,18 @@ class OSpecies:
     diag: bool
 
 
+def damping_profile(nz: int, n: int) -> np.ndarray:
+    """Per-node factor of the absorbing layers: sin^2(pi s / (2n)) at the n
+    nodes nearest each end (s = distance in cells from the end node), 1 in
+    between."""
+    w = np.ones(nz)
+    s = np.arange(n)
+    ramp = np.sin(0.5 * np.pi * s / n) ** 2
+    w[:n] = ramp
+    w[nz - 1 - s] = ramp
+    return w
+
+
 class OracleSim:
     def __init__(self, wl, current_correction: bool = True):
         self.nz, self.nr, self.M = wl.nz, wl.nr, wl.n_modes
@@ -61,6 +84,8 @@ class OracleSim:
         self.moving_window = wl.moving_window
         self.correct = current_correction
         self.filter = int(getattr(wl, "filter", 0))
+        self.damp = int(getattr(wl, "damp_cells", 0))
+        self.galilean = bool(getattr(wl, "galilean", False))
         self.n_shift = 0
         self.hankel = [sp.HankelPair(m, wl.nr, wl.dr, wl.kperp_grid) for m in range(self.M)]
         self.kzm = sp.kz_modified(sp.kz_grid(wl.nz, wl.dz), wl.dz, wl.order)[None, :]
@@ -86,6 +111,8 @@ class OracleSim:
         for s in wl.species:
             if getattr(s, "self_field", False) and s.mobile and s.x.size:
                 self.add_beam_field(s)
+        # with absorbing layers the real-space fields are the state from the start
+        self._real_pending = self.damp > 0
 
     def add_beam_field(self, s):
         """Add the field of a cold beam's charge moving rigidly along z at its
@@ -174,13 +201,26 @@ class OracleSim:
             Jh = tuple(hk.forward(self.J[m, c], nus[c]) for c in range(3))
             r0 = hk.forward(self.rho_old[m], m)
             r1 = hk.forward(self.rho_new[m], m)
+            if self.galilean:
+                # the grid moves one cell per step: rho^{n+1} onto the grid at
+                # t^{n+1}, J onto the grid at t^{n+1/2}
+                one, half = sp.galilean_translations(self.kz, self.dz)
+                r1 = one[None, :] * r1
+                Jh = tuple(half[None, :] * j for j in Jh)
             if self.filter:
                 f = sp.binomial_filter(self.kz, self.dz, hk.k, self.dr, self.filter)
                 Jh = tuple(f * j for j in Jh)
                 r0, r1 = f * r0, f * r1
-            if self.correct:
-                Jh = sp.current_correction(Jh, r0, r1, self.dt, kp, self.kzm)
-            En, Bn = sp.psatd_push(tuple(self.Eh[m]), tuple(self.Bh[m]), Jh, r0, r1, self.dt, kp, self.kzm)
+            if self.galilean:
+                v = self.dz / self.dt
+                if self.correct:
+                    Jh = sp.current_correction_galilean(Jh, r0, r1, self.dt, kp, self.kzm, v)
+                En, Bn = sp.psatd_push_galilean(tuple(self.Eh[m]), tuple(self.Bh[m]), Jh, r0, r1, self.dt, kp,
+                                                self.kzm, v)
+            else:
+                if self.correct:
+                    Jh = sp.current_correction(Jh, r0, r1, self.dt, kp, self.kzm)
+                En, Bn = sp.psatd_push(tuple(self.Eh[m]), tuple(self.Bh[m]), Jh, r0, r1, self.dt, kp, self.kzm)
             for c in range(3):
                 self.Eh[m, c] = En[c]
                 self.Bh[m, c] = Bn[c]
@@ -189,12 +229,23 @@ class OracleSim:
         self._real_pending = False
         if self.moving_window:
             self.move_window()
+        if self.damp:
+            self.damp_edges()
+
+    # -- stage 7: absorbing layers ----------------------------------------
+    def damp_edges(self):
+        w = damping_profile(self.nz, self.damp)
+        self.E *= w
+        self.B *= w
+        self._real_pending = True
 
     # -- stage 6: moving window -------------------------------------------
     def move_window(self):
         self.n_shift += 1
         self.zmin = self.zmin0 + self.n_shift * self.dz
-        if not self._real_pending:
+        if self.galilean:
+            pass          # the Galilean update already put E, B on the moved grid
+        elif not self._real_pending:
             # a one-cell periodic shift toward the tail multiplies the z
             # spectrum by exp(i k_z dz); removing the departed column first
             # (a delta in z: the same radial transform at every k_z) leaves
@@ -207,9 +258,10 @@ class OracleSim:
                     for c in range(3):
                         tail = hk.F[nus[c]] @ F[m, c, :, 0]
                         Fh[m, c] = ramp * (Fh[m, c] - tail[:, None])
-        for F in (self.E, self.B):
-            F[..., :-1] = F[..., 1:].copy()
-            F[..., -1] = 0.0
+        if not self.galilean:
+            for F in (self.E, self.B):
+                F[..., :-1] = F[..., 1:].copy()
+                F[..., -1] = 0.0
         for s in self.species:
             keep = s.z >= self.zmin
             for a in ("x", "y", "z", "ux", "uy", "uz", "w"):

@@ -200,6 +200,77 @@ def psatd_push(E, B, J, rho_old, rho_new, dt, kp, kzm):
     return En, Bn
 
 
+# --- Galilean PSATD (the scheme the paper names as intrinsically stable for
+# drifting plasmas, Sec. "Finite order pseudo-spectral solvers") -------------
+# Fields expressed in coordinates z' = z - v t that move with the grid obey
+# Maxwell's equations plus the advection term v d/dz', which in spectral form
+# adds i w F with w = [k_z] v (the same order-p derivative as in Maxwell's
+# curl).  With J constant over the step in those coordinates the update is the
+# exact solution of
+#   dE/dt = curl B - J + i w E,   dB/dt = -curl E + i w B,
+#   d rho/dt = -div J + i w rho  (continuity in the moving coordinates).
+def phase_integral(a, dt):
+    """int_0^dt exp(i a u) du = dt exp(i a dt/2) sinc(a dt/2)."""
+    return dt * np.exp(0.5j * a * dt) * np.sinc(a * dt / (2.0 * np.pi))
+
+
+def galilean_coefficients(kp, kzm, dt, v):
+    """theta^2 = exp(i w dt), C, S, and the source integrals
+    X1 = int_0^dt exp(i w u) cos(k u) du, X2 = int_0^dt exp(i w u) sin(k u) du,
+    phi = int_0^dt exp(i w u) du, with w = [k_z] v, k = sqrt(k_perp^2 + [k_z]^2)."""
+    k = np.sqrt(kp ** 2 + kzm ** 2)
+    w = kzm * v
+    pp, pm = phase_integral(w + k, dt), phase_integral(w - k, dt)
+    return (np.exp(1j * w * dt), np.cos(k * dt), np.sin(k * dt), 0.5 * (pp + pm), (pp - pm) / 2j,
+            phase_integral(w, dt))
+
+
+def current_correction_galilean(J, rho_old, rho_new, dt, kp, kzm, v):
+    """J <- J + grad F with F chosen so that afterwards
+    div J = (theta^2 rho_old - rho_new) / phi, the continuity equation in the
+    moving coordinates integrated over the step with J constant
+    (rho_new = theta^2 rho_old - phi div J)."""
+    th2, _, _, _, _, ph = galilean_coefficients(kp, kzm, dt, v)
+    k2 = kp ** 2 + kzm ** 2
+    F = (div(J, kp, kzm) + (rho_new - th2 * rho_old) / ph) / k2
+    g = grad(F, kp, kzm)
+    return tuple(J[c] + g[c] for c in range(3))
+
+
+def psatd_push_galilean(E, B, J, rho_old, rho_new, dt, kp, kzm, v):
+    """One Galilean PSATD step (rho_old, E, B on the grid at t^n; rho_new on the
+    grid at t^{n+1}; J in the moving coordinates):
+      E' = th2 C E + th2 (S/k) curl B - X1 J
+           + (1/k^2) grad[(X1/phi - 1) rho_new + th2 (C - X1/phi) rho_old]
+      B' = th2 C B - th2 (S/k) curl E + (X2/k) curl J
+    The transverse part is the exact solution above; the longitudinal part is
+    fixed by Gauss's law at t^{n+1} given Gauss's law at t^n and the continuity
+    of current_correction_galilean.  v = 0 gives psatd_push."""
+    th2, C, S, X1, X2, ph = galilean_coefficients(kp, kzm, dt, v)
+    k = np.sqrt(kp ** 2 + kzm ** 2)
+    cB = curl(B, kp, kzm)
+    cE = curl(E, kp, kzm)
+    cJ = curl(J, kp, kzm)
+    g = grad((X1 / ph - 1.0) * rho_new + th2 * (C - X1 / ph) * rho_old, kp, kzm)
+    En = tuple(th2 * C * E[c] + th2 * (S / k) * cB[c] - X1 * J[c] + g[c] / k ** 2 for c in range(3))
+    Bn = tuple(th2 * C * B[c] - th2 * (S / k) * cE[c] + (X2 / k) * cJ[c] for c in range(3))
+    return En, Bn
+
+
+def galilean_translations(kz, dz, n_shift=1.0):
+    """Spectral factors that move a field from the grid at t^n to the grid
+    n_shift cells ahead (periodic along z): exp(i k_z n_shift dz) on the DFT
+    wavenumbers, for whole and half cells.  A half-cell move of the Nyquist
+    component of a real signal has no real value; it is taken as the average of
+    its two readings, cos(pi/2) = 0 (as the derivative symbol there)."""
+    kz = np.asarray(kz)
+    one = np.exp(1j * kz * dz * n_shift)
+    half = np.exp(0.5j * kz * dz * n_shift)
+    nyq = np.abs(np.abs(kz * dz) - np.pi) <= 1e-12 * np.pi
+    half = np.where(nyq, 0.0, half)
+    return one, half
+
+
 def binomial_filter(kz, dz, kperp, dr, passes=1):
     """`passes` (1/4, 1/2, 1/4) smoothing passes along z and along r in spectral
     form, [cos^2(k_z dz/2) cos^2(k_perp dr/2)]^passes, shape [k_perp, k_z] (an

@@ -1,5 +1,6 @@
 // C interface of the quasi-cylindrical order-p PSATD PIC cycle (see include/pic.h).
 #include <math.h>
+#include <stddef.h>
 #include <string.h>
 
 #include <algorithm>
@@ -41,6 +42,7 @@ __global__ void k_state_init(DevState* st, double zmin, int n_part) {
   st->n_live = n_part;
   st->pending_shift = 0;
   st->overflow = 0;
+  st->nonfinite = 0;
 }
 
 __global__ void k_set_npart(DevState* st, int n) {
@@ -133,6 +135,7 @@ struct pic_ctx {
   bool graph_ok;
   int graph_bm, graph_chunk;
   bool graph_shift;
+  int graph_cur;         // particle buffer the captured steps start from
 };
 
 namespace {
@@ -166,6 +169,8 @@ int validate(const pic_config* c, const pic_species* s, int ns) {
   if (c->kperp_grid < 0 || c->kperp_grid > 2) return PIC_EINVAL;
   if (c->hankel_prec < 0 || c->hankel_prec > 2) return PIC_EINVAL;
   if (c->filter < 0 || c->filter > 4) return PIC_EINVAL;
+  if (c->damp_cells < 0 || c->damp_cells > c->nz / 4) return PIC_EINVAL;
+  if (c->galilean != 0 && (c->galilean != 1 || !c->moving_window)) return PIC_EINVAL;
   if (ns < 0 || ns > kMaxSpecies || (ns > 0 && !s)) return PIC_EINVAL;
   for (int i = 0; i < ns; ++i) {
     const pic_species& p = s[i];
@@ -346,14 +351,18 @@ int check_launch() {
   return e == hipSuccess ? PIC_OK : PIC_EHIP;
 }
 
+static_assert(offsetof(DevState, nonfinite) == offsetof(DevState, overflow) + sizeof(int32_t),
+              "sync reads both flags with one copy");
+
 int sync(pic_ctx* x) {
   hipError_t e = hipStreamSynchronize(x->stream);
   if (e != hipSuccess) return PIC_EHIP;
   int rc = check_launch();
   if (rc) return rc;
-  int ovf = 0;
-  if (hipMemcpy(&ovf, &x->st->overflow, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
-  return ovf ? PIC_ENOSPC : PIC_OK;   // particle capacity or deposit work list exceeded
+  int flags[2] = {0, 0};   // overflow, nonfinite (adjacent in DevState)
+  if (hipMemcpy(flags, &x->st->overflow, sizeof(flags), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+  if (flags[0]) return PIC_ENOSPC;    // particle capacity or deposit work list exceeded
+  return flags[1] ? PIC_ENUMERIC : PIC_OK;   // a split-precision Hankel product overflowed
 }
 
 hipEvent_t take_event(pic_ctx* x) {
@@ -406,7 +415,7 @@ void forward_transform(pic_ctx* x, float2* src_base, int c0, int nc, int pt_entr
   int batch = nc * M;
   Phase ph(x, PIC_T_DHT_FWD);
   launch_dht_gemm(tab, tab + batch, (float* const*)(tab + 2 * batch), batch, x->nr, 2 * x->nz,
-                  x->cfg.hankel_prec, x->gemm_bm, x->stream);
+                  x->cfg.hankel_prec, x->gemm_bm, x->stream, &x->st->nonfinite);
 }
 
 }  // namespace
@@ -771,7 +780,8 @@ int pic_spectral_push(pic_ctx* x) {
   hipStream_t s = x->stream;
   const int M = x->M, nr = x->nr, nz = x->nz;
   bool apply_shift = x->spec_pending;
-  if (x->eb_stale) {
+  // with absorbing layers the damped real-space E, B are the state
+  if (x->eb_stale || x->cfg.damp_cells > 0) {
     forward_transform(x, x->real, 0, 6, x->pt_fwd_eb);
     x->eb_stale = false;
     apply_shift = false;
@@ -780,7 +790,7 @@ int pic_spectral_push(pic_ctx* x) {
   {
     Phase ph(x, PIC_T_PSATD);
     launch_psatd(x->spec, x->kperp, x->kzm, x->tw, x->tailhat, nz, nr, M, x->cfg.dt, apply_shift,
-                 x->cfg.current_correction != 0, x->kz, x->cfg.dz, x->cfg.dr, x->cfg.filter, s);
+                 x->cfg.current_correction != 0, x->kz, x->cfg.dz, x->cfg.dr, x->cfg.filter, x->cfg.galilean != 0, s);
   }
   x->spec_pending = false;
   {
@@ -788,12 +798,19 @@ int pic_spectral_push(pic_ctx* x) {
     const float* const* tab = x->ptr_tab + x->pt_inv_eb;
     int batch = 6 * M;
     launch_dht_gemm(tab, tab + batch, (float* const*)(tab + 2 * batch), batch, nr, 2 * nz, x->cfg.hankel_prec,
-                    x->gemm_bm, s);
+                    x->gemm_bm, s, &x->st->nonfinite);
   }
   const bool mw = x->cfg.moving_window != 0;
+  // the Galilean update leaves E, B on the moved grid: no shift of their own
+  const bool shift_fields = mw && !x->cfg.galilean;
   {
     Phase ph(x, PIC_T_FFT_INV);
-    launch_fft(fld(x->tmp, x, 0, 0), fld(x->real, x, 0, 0), x->tw, nz, (int64_t)6 * M * nr, true, mw, x->tail, s);
+    launch_fft(fld(x->tmp, x, 0, 0), fld(x->real, x, 0, 0), x->tw, nz, (int64_t)6 * M * nr, true, shift_fields,
+               x->tail, s);
+  }
+  if (x->cfg.damp_cells > 0) {
+    Phase ph(x, PIC_T_WINDOW);
+    launch_damp(fld(x->real, x, 0, 0), nz, (int64_t)6 * M * nr, x->cfg.damp_cells, s);
   }
   {
     Phase ph(x, PIC_T_PACK);
@@ -803,7 +820,7 @@ int pic_spectral_push(pic_ctx* x) {
     Phase ph(x, PIC_T_WINDOW);
     launch_tail_transform(x->tail, x->tailhat, x->ptr_tab + x->pt_tail, nr, 6 * M, x->st, x->cfg.z_min, x->cfg.dz, s);
     if (x->inj.total > 0) launch_inject(x->parts[x->cur], x->st, x->g, x->inj, (int)x->cap, s);
-    x->spec_pending = true;
+    x->spec_pending = shift_fields;
     x->n_shift += 1;
   }
   for (int m = 0; m < M; ++m) x->src_set[m] = 0;
@@ -1142,6 +1159,7 @@ int capture_graph(pic_ctx* x) {
   x->graph_bm = x->gemm_bm;
   x->graph_chunk = x->dep.chunk;
   x->graph_shift = x->spec_pending;
+  x->graph_cur = x->cur;
   return PIC_OK;
 }
 
@@ -1160,10 +1178,20 @@ int graph_steps(pic_ctx* x, int n) {
     if (rc) return rc;
     --n;
   }
-  if (n >= 2 && !(x->graph_ok && x->graph_bm == x->gemm_bm && x->graph_chunk == x->dep.chunk &&
-                  x->graph_shift == x->spec_pending)) {
-    rc = capture_graph(x);
-    if (rc) return rc;
+  if (n >= 2) {
+    // the captured steps read the particle buffer that was current at the
+    // capture: after an odd number of steps since, an odd remainder is taken
+    // first (eagerly), else the graph is captured again
+    const bool params = x->graph_ok && x->graph_bm == x->gemm_bm && x->graph_chunk == x->dep.chunk &&
+                        x->graph_shift == x->spec_pending;
+    if (params && x->cur != x->graph_cur && (n & 1)) {
+      if ((rc = pic_step(x, 1)) != PIC_OK) return rc;
+      --n;
+    }
+    if (!params || x->cur != x->graph_cur) {
+      rc = capture_graph(x);
+      if (rc) return rc;
+    }
   }
   for (; n >= 2; n -= 2) {
     if (hipGraphLaunch(x->graph, x->stream) != hipSuccess) return PIC_EHIP;
@@ -1181,20 +1209,214 @@ int pic_step_graph(pic_ctx* x, int n) {
   return graph_steps(x, n);
 }
 
-int pic_batch_step(pic_ctx* const* ctxs, int n_ctx, int n) {
-  if (!ctxs || n_ctx < 0 || n < 0) return PIC_EINVAL;
-  for (int c = 0; c < n_ctx; ++c)
-    if (!ctxs[c]) return PIC_EINVAL;
-  // round-robin two steps at a time over the contexts' own streams, so
-  // independent instances overlap on the GPU
-  for (int done = 0; done < n; done += 2) {
-    const int k = (n - done) >= 2 ? 2 : 1;
-    for (int c = 0; c < n_ctx; ++c) {
-      int rc = graph_steps(ctxs[c], k);
-      if (rc) return rc;
-    }
+}  // extern "C"
+
+// A batch of independent contexts advanced by one graph: two steps of every
+// context, each on its own stream, forked from and joined back into the
+// batch's lead stream inside one capture, so a replay is one launch for the
+// whole batch and the GPU overlaps the instances' kernels.
+struct pic_batch {
+  std::vector<pic_ctx*> ctx;
+  hipStream_t lead = nullptr;
+  hipEvent_t ev_lead = nullptr;          // lead stream -> context streams
+  std::vector<hipEvent_t> ev_ctx;        // context streams -> lead stream
+  hipGraphExec_t exec = nullptr;
+  // launch parameters and current particle buffer of every context when the
+  // graph was captured
+  std::vector<int> bm, chunk, cur;
+  std::vector<char> shift;
+};
+
+namespace {
+
+struct HostMirror {
+  int cur, phase;
+  int64_t steps, n_shift;
+  bool spec_pending, eb_stale, rho_carry;
+};
+
+HostMirror save_mirror(const pic_ctx* x) {
+  return {x->cur, x->phase, x->steps, x->n_shift, x->spec_pending, x->eb_stale, x->rho_carry};
+}
+
+void restore_mirror(pic_ctx* x, const HostMirror& h) {
+  x->cur = h.cur;
+  x->phase = h.phase;
+  x->steps = h.steps;
+  x->n_shift = h.n_shift;
+  x->spec_pending = h.spec_pending;
+  x->eb_stale = h.eb_stale;
+  x->rho_carry = h.rho_carry;
+}
+
+bool batch_params(const pic_batch* b) {
+  if (!b->exec) return false;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    const pic_ctx* x = b->ctx[i];
+    if (x->gemm_bm != b->bm[i] || x->dep.chunk != b->chunk[i] || (char)x->spec_pending != b->shift[i]) return false;
+  }
+  return true;
+}
+
+// 1: every context is on the particle buffer of the capture; -1: every one on
+// the other buffer; 0: mixed
+int batch_parity(const pic_batch* b) {
+  int same = 0;
+  for (size_t i = 0; i < b->ctx.size(); ++i) same += b->ctx[i]->cur == b->cur[i];
+  return same == (int)b->ctx.size() ? 1 : same == 0 ? -1 : 0;
+}
+
+int batch_capture(pic_batch* b) {
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  const size_t n = b->ctx.size();
+  std::vector<HostMirror> saved(n);
+  for (size_t i = 0; i < n; ++i) saved[i] = save_mirror(b->ctx[i]);
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(b->lead, hipStreamCaptureModeThreadLocal) != hipSuccess) return PIC_EHIP;
+  int rc = hipEventRecord(b->ev_lead, b->lead) == hipSuccess ? PIC_OK : PIC_EHIP;
+  for (size_t i = 0; i < n && rc == PIC_OK; ++i) {
+    pic_ctx* x = b->ctx[i];
+    if (hipStreamWaitEvent(x->stream, b->ev_lead, 0) != hipSuccess) rc = PIC_EHIP;
+    if (rc == PIC_OK) rc = pic_step(x, 2);
+    if (rc == PIC_OK && (hipEventRecord(b->ev_ctx[i], x->stream) != hipSuccess ||
+                         hipStreamWaitEvent(b->lead, b->ev_ctx[i], 0) != hipSuccess))
+      rc = PIC_EHIP;
+  }
+  hipError_t e = hipStreamEndCapture(b->lead, &g);
+  for (size_t i = 0; i < n; ++i) restore_mirror(b->ctx[i], saved[i]);
+  if (rc != PIC_OK || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return rc != PIC_OK ? rc : PIC_EHIP;
+  }
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->exec = nullptr;
+    return PIC_EHIP;
+  }
+  for (size_t i = 0; i < n; ++i) {
+    b->bm[i] = b->ctx[i]->gemm_bm;
+    b->chunk[i] = b->ctx[i]->dep.chunk;
+    b->shift[i] = (char)b->ctx[i]->spec_pending;
+    b->cur[i] = b->ctx[i]->cur;
   }
   return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_batch_create(pic_ctx* const* ctxs, int n_ctx, pic_batch** out) {
+  if (!out) return PIC_EINVAL;
+  *out = nullptr;
+  if (!ctxs || n_ctx < 1) return PIC_EINVAL;
+  for (int c = 0; c < n_ctx; ++c) {
+    if (!ctxs[c] || !ctxs[c]->stream) return PIC_EINVAL;
+    for (int d = 0; d < c; ++d)
+      if (ctxs[d] == ctxs[c]) return PIC_EINVAL;
+  }
+  pic_batch* b = new pic_batch;
+  b->ctx.assign(ctxs, ctxs + n_ctx);
+  b->bm.assign(n_ctx, 0);
+  b->chunk.assign(n_ctx, 0);
+  b->cur.assign(n_ctx, 0);
+  b->shift.assign(n_ctx, 0);
+  b->ev_ctx.assign(n_ctx, nullptr);
+  bool ok = hipStreamCreateWithFlags(&b->lead, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ev_lead, hipEventDisableTiming) == hipSuccess;
+  for (int c = 0; c < n_ctx && ok; ++c)
+    ok = hipEventCreateWithFlags(&b->ev_ctx[c], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)pic_batch_free(b);
+    return PIC_EHIP;
+  }
+  *out = b;
+  return PIC_OK;
+}
+
+int pic_batch_run(pic_batch* b, int n) {
+  if (!b || n < 0) return PIC_EINVAL;
+  for (pic_ctx* x : b->ctx) {
+    if (x->phase != 0) return PIC_ESTATE;
+    if (x->timing) return PIC_EINVAL;
+    for (int m = 0; m < x->M; ++m)
+      if (x->src_set[m]) return PIC_ESTATE;
+  }
+  if (n == 0) return PIC_OK;
+  int rc = PIC_OK;
+  // one eager step of every context settles any one-time work (as in
+  // pic_step_graph); the contexts stay in step with each other
+  bool settle = false;
+  for (pic_ctx* x : b->ctx) settle = settle || x->steps == 0 || x->eb_stale || !x->rho_carry;
+  if (settle) {
+    for (pic_ctx* x : b->ctx)
+      if ((rc = pic_step(x, 1)) != PIC_OK) return rc;
+    --n;
+  }
+  if (n >= 2) {
+    // as in pic_step_graph: the graph reads the particle buffers current at
+    // its capture
+    const bool params = batch_params(b);
+    if (params && batch_parity(b) == -1 && (n & 1)) {
+      for (pic_ctx* x : b->ctx)
+        if ((rc = pic_step(x, 1)) != PIC_OK) return rc;
+      --n;
+    }
+    if ((!params || batch_parity(b) != 1) && (rc = batch_capture(b)) != PIC_OK) return rc;
+    // the replays start after the work already queued on every context's
+    // stream, and that stream's later work starts after the replays
+    for (size_t i = 0; i < b->ctx.size(); ++i)
+      if (hipEventRecord(b->ev_ctx[i], b->ctx[i]->stream) != hipSuccess ||
+          hipStreamWaitEvent(b->lead, b->ev_ctx[i], 0) != hipSuccess)
+        return PIC_EHIP;
+    for (; n >= 2; n -= 2) {
+      if (hipGraphLaunch(b->exec, b->lead) != hipSuccess) return PIC_EHIP;
+      for (pic_ctx* x : b->ctx) {
+        x->steps += 2;
+        if (x->cfg.moving_window) x->n_shift += 2;
+      }
+    }
+    if (hipEventRecord(b->ev_lead, b->lead) != hipSuccess) return PIC_EHIP;
+    for (pic_ctx* x : b->ctx)
+      if (hipStreamWaitEvent(x->stream, b->ev_lead, 0) != hipSuccess) return PIC_EHIP;
+  }
+  if (n == 1)
+    for (pic_ctx* x : b->ctx)
+      if ((rc = pic_step(x, 1)) != PIC_OK) return rc;
+  return check_launch();
+}
+
+int pic_batch_free(pic_batch* b) {
+  if (!b) return PIC_EINVAL;
+  int rc = PIC_OK;
+  if (b->lead && hipStreamSynchronize(b->lead) != hipSuccess) rc = PIC_EHIP;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->ev_lead) (void)hipEventDestroy(b->ev_lead);
+  for (hipEvent_t e : b->ev_ctx)
+    if (e) (void)hipEventDestroy(e);
+  if (b->lead) (void)hipStreamDestroy(b->lead);
+  delete b;
+  return rc;
+}
+
+int pic_batch_step(pic_ctx* const* ctxs, int n_ctx, int n) {
+  if (!ctxs || n_ctx < 0 || n < 0) return PIC_EINVAL;
+  if (n_ctx == 0 || n == 0) {
+    for (int c = 0; c < n_ctx; ++c)
+      if (!ctxs[c]) return PIC_EINVAL;
+    return PIC_OK;
+  }
+  pic_batch* b = nullptr;
+  int rc = pic_batch_create(ctxs, n_ctx, &b);
+  if (rc) return rc;
+  rc = pic_batch_run(b, n);
+  const int rc2 = pic_batch_free(b);
+  return rc ? rc : rc2;
 }
 
 int pic_autotune(pic_ctx* x, int steps_per_trial, pic_tuning* best, double* best_ms) {

@@ -27,7 +27,8 @@ struct DevState {
   int32_t n_live;       // particles kept by the last sort (sorted prefix)
   int32_t pending_shift;// spectral E, B still need the last window move applied
   int32_t overflow;     // capacity exceeded at an injection
-  int32_t pad[2];
+  int32_t nonfinite;    // a split-precision Hankel product produced inf/NaN
+  int32_t pad;
 };
 
 // Grid constants passed by value to kernels.

@@ -175,7 +175,8 @@ __device__ __forceinline__ floatx16 mfma16(typename Split<F16>::vec a, typename 
 
 template <int BM, int BN, bool F16>
 __global__ __launch_bounds__(256) void k_gemm_split(const float* const* __restrict__ AT, const float* const* __restrict__ X,
-                                                    float* const* __restrict__ Y, int n, int ncols) {
+                                                    float* const* __restrict__ Y, int n, int ncols,
+                                                    int* __restrict__ nonfinite) {
   using T = GemmTile<BM, BN>;
   using S = Split<F16>;
   __shared__ float As[2][T::A_ELEMS];
@@ -240,6 +241,18 @@ __global__ __launch_bounds__(256) void k_gemm_split(const float* const* __restri
     for (int j = 0; j < BN; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] += acl[i][j][r] * inv;
+  if (nonfinite) {
+    // an operand beyond the halves' range (FP16: 65504) gives inf or NaN;
+    // flag it for the caller's next synchronizing call
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) bad = bad || !isfinite(acc[i][j][r]);
+    if (__ballot(bad) != 0 && lane == 0) atomicOr(nonfinite, 1);
+  }
   store_out<BM, BN>(y, ncols, m0, n0, acc);
 }
 
@@ -248,15 +261,15 @@ __global__ __launch_bounds__(256) void k_gemm_split(const float* const* __restri
 // ---------------------------------------------------------------------------
 template <int BM, int BN>
 static void launch_tile(const float* const* at, const float* const* x, float* const* y, int batch, int n, int ncols,
-                        int prec, hipStream_t s) {
+                        int prec, int* nonfinite, hipStream_t s) {
   using T = GemmTile<BM, BN>;
   dim3 grid(ncols / T::NT, n / T::MT, batch);
   if (prec == 0)
     hipLaunchKernelGGL((k_gemm_f32<BM, BN>), grid, dim3(256), 0, s, at, x, y, n, ncols);
   else if (prec == 1)
-    hipLaunchKernelGGL((k_gemm_split<BM, BN, false>), grid, dim3(256), 0, s, at, x, y, n, ncols);
+    hipLaunchKernelGGL((k_gemm_split<BM, BN, false>), grid, dim3(256), 0, s, at, x, y, n, ncols, nonfinite);
   else
-    hipLaunchKernelGGL((k_gemm_split<BM, BN, true>), grid, dim3(256), 0, s, at, x, y, n, ncols);
+    hipLaunchKernelGGL((k_gemm_split<BM, BN, true>), grid, dim3(256), 0, s, at, x, y, n, ncols, nonfinite);
 }
 
 // tile choice: rows per workgroup 32*BM with BM in {4, 2, 1} dividing n; BN = 1.
@@ -267,11 +280,11 @@ int gemm_tile_bm(int n, int pref_bm) {
 }
 
 void launch_dht_gemm(const float* const* at, const float* const* x, float* const* y, int batch, int n, int ncols,
-                     int prec, int pref_bm, hipStream_t s) {
+                     int prec, int pref_bm, hipStream_t s, int* nonfinite) {
   int bm = gemm_tile_bm(n, pref_bm);
-  if (bm == 4) launch_tile<4, 1>(at, x, y, batch, n, ncols, prec, s);
-  else if (bm == 2) launch_tile<2, 1>(at, x, y, batch, n, ncols, prec, s);
-  else launch_tile<1, 1>(at, x, y, batch, n, ncols, prec, s);
+  if (bm == 4) launch_tile<4, 1>(at, x, y, batch, n, ncols, prec, nonfinite, s);
+  else if (bm == 2) launch_tile<2, 1>(at, x, y, batch, n, ncols, prec, nonfinite, s);
+  else launch_tile<1, 1>(at, x, y, batch, n, ncols, prec, nonfinite, s);
 }
 
 }  // namespace pic

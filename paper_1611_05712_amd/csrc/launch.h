@@ -84,12 +84,16 @@ void fft_config(int nz, int& rows_per_wg, size_t& lds);
 // as their input (rho^{n+1} - rho^n without an intermediate array).
 void launch_fft(const float2* in, float2* out, const float2* tw, int nz, int64_t rows, bool inverse, bool shift,
                 float2* tail, hipStream_t s, int64_t diff_lo = 0, int64_t diff_hi = 0, int64_t diff_off = 0);
+// Absorbing layers: columns [0, nd) and [nz - nd, nz) of `rows` real-space rows
+// scaled by sin^2(pi s / (2 nd)), s the distance from the end column.
+void launch_damp(float2* rows_base, int nz, int64_t rows, int nd, hipStream_t s);
 int gemm_tile_bm(int n, int pref_bm);
+// nonfinite (may be null): set to 1 when a split-precision product yields inf/NaN
 void launch_dht_gemm(const float* const* at, const float* const* x, float* const* y, int batch, int n, int ncols,
-                     int prec, int pref_bm, hipStream_t s);
+                     int prec, int pref_bm, hipStream_t s, int* nonfinite = nullptr);
 void launch_psatd(float2* spec, const double* kperp, const double* kzm, const float2* tw, const float2* tailhat,
                   int nz, int nr, int M, double dt, bool apply_shift, bool correct, const double* kz_grid, double dz,
-                  double dr, int filter, hipStream_t s);
+                  double dr, int filter, bool galilean, hipStream_t s);
 void launch_beam_field(float2* spec, const double* kperp, const double* kzm, int nz, int nr, int M, double gamma,
                        double beta, hipStream_t s);
 // tail column transform; with st non-null also one window move of the device state

@@ -26,7 +26,8 @@ EXPORTED = (
     "pic_step", "pic_sync", "pic_diagnostics", "pic_get_field", "pic_set_field",
     "pic_num_particles", "pic_get_particles", "pic_get_state", "pic_free", "pic_strerror",
     "pic_fft_z", "pic_dht_gemm", "pic_timing_enable", "pic_timing_read",
-    "pic_get_tuning", "pic_set_tuning", "pic_step_graph", "pic_batch_step", "pic_autotune",
+    "pic_get_tuning", "pic_set_tuning", "pic_step_graph", "pic_batch_step", "pic_batch_create",
+    "pic_batch_run", "pic_batch_free", "pic_autotune",
     "pic_diagnostics_slices", "pic_diagnostics_slices_noalloc",
     "pic_mlp_num_params", "pic_mlp_workspace_bytes", "pic_mlp_init", "pic_mlp_forward", "pic_mlp_loss_grad",
     "pic_mlp_train", "pic_mlp_get_params", "pic_mlp_set_params", "pic_mlp_steps", "pic_mlp_sync", "pic_mlp_free",
@@ -47,7 +48,7 @@ class pic_config(ctypes.Structure):
                 ("dt", ctypes.c_double), ("z_min", ctypes.c_double),
                 ("moving_window", ctypes.c_int32), ("kperp_grid", ctypes.c_int32),
                 ("hankel_prec", ctypes.c_int32), ("current_correction", ctypes.c_int32),
-                ("filter", ctypes.c_int32)]
+                ("filter", ctypes.c_int32), ("damp_cells", ctypes.c_int32), ("galilean", ctypes.c_int32)]
 
 
 class pic_tuning(ctypes.Structure):
@@ -131,6 +132,9 @@ def load(path: str = LIB_PATH):
     L.pic_set_tuning.argtypes = [vp, ctypes.POINTER(pic_tuning)]
     L.pic_step_graph.argtypes = [vp, i32]
     L.pic_batch_step.argtypes = [ctypes.POINTER(vp), i32, i32]
+    L.pic_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    L.pic_batch_run.argtypes = [vp, i32]
+    L.pic_batch_free.argtypes = [vp]
     L.pic_autotune.argtypes = [vp, i32, ctypes.POINTER(pic_tuning), ctypes.POINTER(ctypes.c_double)]
     cfgp = ctypes.POINTER(pic_mlp_config)
     L.pic_mlp_num_params.argtypes = [cfgp, ctypes.POINTER(i64)]
@@ -180,13 +184,15 @@ class Simulation:
 
     def __init__(self, nz, nr, n_modes, order, dz, dr, dt, z_min, species: Sequence,
                  moving_window=False, kperp_grid=KPERP_JM_ZEROS, hankel_prec=H_FP32,
-                 current_correction=True, max_particles=0, device="cuda:0", stream=None, filter=0):
+                 current_correction=True, max_particles=0, device="cuda:0", stream=None, filter=0,
+                 damp_cells=0, galilean=False):
         import torch
         L = load()
         self._L = L
         self.device = torch.device(device)
         self.cfg = pic_config(nz, nr, n_modes, order, dz, dr, dt, z_min, int(bool(moving_window)),
-                              kperp_grid, hankel_prec, int(bool(current_correction)), int(filter))
+                              kperp_grid, hankel_prec, int(bool(current_correction)), int(filter),
+                              int(damp_cells), int(bool(galilean)))
         self.nz, self.nr, self.n_modes = nz, nr, n_modes
         self.species_names = [s.name for s in species]
         self._keep = []
@@ -227,6 +233,8 @@ class Simulation:
     @classmethod
     def from_workload(cls, wl, **kw):
         kw.setdefault("filter", getattr(wl, "filter", 0))
+        kw.setdefault("damp_cells", getattr(wl, "damp_cells", 0))
+        kw.setdefault("galilean", getattr(wl, "galilean", False))
         return cls(wl.nz, wl.nr, wl.n_modes, wl.order, wl.dz, wl.dr, wl.dt, wl.zmin, wl.species,
                    moving_window=wl.moving_window, kperp_grid=wl.kperp_grid, **kw)
 
@@ -370,13 +378,42 @@ class Simulation:
 # kernel-level entry points
 # ---------------------------------------------------------------------------
 def batch_step(sims: Sequence["Simulation"], n: int):
-    """n steps of every simulation, their graph replays interleaved over the
-    simulations' own streams (pic_batch_step)."""
+    """n steps of every simulation as replays of one graph that holds two
+    steps of all of them (pic_batch_step); returns once they are done."""
     if not sims:
         return
     L = load()
     arr = (ctypes.c_void_p * len(sims))(*[s._ctx for s in sims])
     _check(L.pic_batch_step(arr, len(sims), int(n)), "pic_batch_step")
+
+
+class Batch:
+    """Independent simulations advanced together by one captured graph
+    (pic_batch_create / pic_batch_run / pic_batch_free); the simulations must
+    stay open while the batch is."""
+
+    def __init__(self, sims: Sequence["Simulation"]):
+        self._L = load()
+        self.sims = list(sims)
+        arr = (ctypes.c_void_p * len(self.sims))(*[s._ctx for s in self.sims])
+        h = ctypes.c_void_p()
+        _check(self._L.pic_batch_create(arr, len(self.sims), ctypes.byref(h)), "pic_batch_create")
+        self._h = h
+
+    def run(self, n: int):
+        """n steps of every simulation (asynchronous)."""
+        _check(self._L.pic_batch_run(self._h, int(n)), "pic_batch_run")
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, None
+            _check(self._L.pic_batch_free(h), "pic_batch_free")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fft_z(t, inverse: bool = False, stream=None):

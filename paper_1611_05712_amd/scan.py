@@ -1,10 +1,10 @@
 """Parameter scans: many independent runs of the PIC cycle on one GPU.
 
 Each run is its own context (own workspace and stream).  `run_batched`
-advances all of them together: per context two steps at a time as replays of
-its captured HIP graph, interleaved over the contexts' streams so small runs
-overlap on the GPU (pic_batch_step); the launch parameters of each context are
-first chosen by the library's autotuner.  The scan's figure of merit is the
+advances all of them together as replays of one HIP graph that holds two
+steps of every context, each on its own stream (pic_batch_step), so one launch
+advances the whole batch and small runs overlap on the GPU; the launch
+parameters of each context are first chosen by the library's autotuner.  The scan's figure of merit is the
 witness slice energy spread, the quantity the paper tracks against the
 stencil order (Sec. "Accurate modeling of plasma accelerators in finite order
 PSATD"): the mean over 0.5 um slices within +-3 sigma_z of the slice gamma

@@ -51,6 +51,23 @@ def test_graph_steps_match_eager(n):
     _moments_close(b, a, "drive")
 
 
+@pytest.mark.parametrize("calls", [(3, 3, 4), (4, 3, 2, 5), (1, 2, 2, 3, 2)])
+def test_graph_steps_across_calls_of_any_length(calls):
+    """Graph stepping split into calls of odd and even length (the replays
+    must start from the particle buffer they were captured with; the
+    workload injects plasma at every window move, so a replay from the other
+    buffer would lose a column): the same as eager steps."""
+    wl = preset("small")
+    a, b = _sim(wl), _sim(wl)
+    a.step(sum(calls))
+    for n in calls:
+        b.step_graph(n)
+    assert a.state() == b.state()
+    assert a.num_particles() == b.num_particles()
+    assert _field_rel(b, a) < 1e-5
+    _moments_close(b, a, "drive")
+
+
 @pytest.mark.parametrize("modes", [1, 3])
 def test_graph_steps_match_eager_other_mode_counts(modes):
     import dataclasses
@@ -100,6 +117,40 @@ def test_batch_matches_individual_runs():
         assert _field_rel(bs, ss) < 1e-5
         name = "drive" if w.name != "tiny" else "bunch"
         _moments_close(bs, ss, name)
+
+
+def test_batch_graph_over_several_runs_and_a_tuning_change():
+    """One graph for three instances (two grids, a finite and the infinite
+    order): runs of 4, then 3 (an odd step runs eagerly), a tuning change of
+    one instance (the graph is captured again), then 2 more; every instance
+    matches its own eager run."""
+    from paper_1611_05712_amd import Batch
+    wls = [preset("small"), preset("tiny"), preset("small", seed=3)]
+    wls[2].order = 0
+    sims = [_sim(w) for w in wls]
+    solo = [_sim(w) for w in wls]
+    b = Batch(sims)
+    b.run(4)
+    b.run(3)
+    sims[0].set_tuning(32, 2048)
+    b.run(2)
+    b.close()
+    for s in solo:
+        s.step(9)
+    for bs, ss, w in zip(sims, solo, wls):
+        assert bs.state() == ss.state()
+        assert _field_rel(bs, ss) < 1e-5
+        name = "drive" if w.name != "tiny" else "bunch"
+        _moments_close(bs, ss, name)
+
+
+def test_batch_rejects_bad_contexts():
+    from paper_1611_05712_amd import Batch, PicError
+    s = _sim(preset("tiny"))
+    with pytest.raises(PicError):
+        Batch([s, s])
+    with pytest.raises(PicError):
+        Batch([])
 
 
 def test_autotune_picks_a_supported_pair_and_keeps_results():

@@ -436,14 +436,21 @@ def _component_errors(sim, o, m):
     return out
 
 
-def _assert_components(errs, tol, m):
+def _assert_components(errs, tol, m, floor=FLOOR, zero_bar=None):
     for name, (rel, frac, rel_top) in errs.items():
-        if frac >= FLOOR:
+        if frac >= floor:
             assert rel < tol, (m, name, rel)
         else:
             # a component that is nearly zero (B_z of mode 0: no azimuthal
             # current in a nearly symmetric run) carries only rounding noise
-            assert rel_top < tol * FLOOR, (m, name, rel_top)
+            assert rel_top < (tol * floor if zero_bar is None else zero_bar), (m, name, rel_top)
+
+
+# With absorbing layers the field state is re-transformed from FP32 real
+# space every step, so a small component carries the FP32 rounding of the
+# others: components below 1e-2 of their mode's largest are held to a few
+# ulps (FP32: 6e-8) of that largest instead of to their own size.
+REAL_STATE = {"floor": 1e-2, "zero_bar": 2e-7}
 
 
 def test_c0_one_step_fields():
@@ -787,3 +794,138 @@ def test_full_cycle_with_binomial_filter():
     for m in range(2):
         for which in ("E", "B"):
             assert _vector_rel(sim, o, m, which) < 1e-5, (m, which)
+
+
+@pytest.mark.parametrize("moving", [False, True])
+def test_spectral_push_with_absorbing_layers_matches_oracle(moving):
+    """Random fields and sources, two spectral pushes with 12-cell absorbing
+    layers (the second push starts from the damped real-space fields), with
+    and without the window move: every (mode, component) against the oracle."""
+    wl = _vacuum(128, 64, 16)
+    wl.damp_cells = 12
+    wl.moving_window = moving
+    F = _random_fields(wl, seed=77)
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    for step in range(2):
+        for m in range(2):
+            for c in range(6, 11):
+                sim.set_field(m, c, F[m, c])
+        if step == 0:
+            for m in range(2):
+                for c in range(6):
+                    sim.set_field(m, c, F[m, c])
+            o.set_fields(F[:, 0:3], F[:, 3:6])
+        sim.spectral_push()
+        o.J = F[:, 6:9].copy()
+        o.rho_old = F[:, 9].copy()
+        o.rho_new = F[:, 10].copy()
+        o.spectral_push()
+    for m in range(2):
+        for c, name in enumerate(COMPS):
+            want = (o.E if c < 3 else o.B)[m, c % 3]
+            assert _rel(sim.get_field(m, name), want) < FIELD_TOL, (m, name)
+        # the layers: both end columns are zero after the last push
+        assert np.abs(sim.get_field(m, "E+")[:, [0, -1]]).max() == 0.0
+
+
+def test_full_cycle_with_absorbing_layers():
+    """The small beam-plasma workload with 8-cell layers, three full cycles:
+    every (mode, component) against the oracle."""
+    wl = preset("small")
+    wl.damp_cells = 8
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.step(3)
+    o.step(3)
+    for m in range(2):
+        errs = _component_errors(sim, o, m)
+        print("damped small mode", m, {k: f"{v[0]:.2e} ({v[1]:.1e})" for k, v in errs.items()})
+        _assert_components(errs, FIELD_TOL, m, **REAL_STATE)
+
+
+@pytest.mark.parametrize("order", [0, 16, 32])
+def test_galilean_spectral_push_matches_oracle(order):
+    """Random fields and sources, one Galilean spectral push (sources moved
+    onto the moving grid, moving-frame correction and update, no window shift
+    of E, B): every (mode, component) against the oracle."""
+    wl = _vacuum(128, 64, order, moving=True)
+    wl.galilean = True
+    F = _random_fields(wl, seed=90 + order)
+    sim = _sim(wl)
+    for m in range(2):
+        for c in range(11):
+            sim.set_field(m, c, F[m, c])
+    sim.spectral_push()
+    o = OracleSim(wl)
+    o.set_fields(F[:, 0:3], F[:, 3:6])
+    o.J = F[:, 6:9].copy()
+    o.rho_old = F[:, 9].copy()
+    o.rho_new = F[:, 10].copy()
+    o.spectral_push()
+    for m in range(2):
+        for c, name in enumerate(COMPS):
+            want = (o.E if c < 3 else o.B)[m, c % 3]
+            assert _rel(sim.get_field(m, name), want) < FIELD_TOL, (order, m, name)
+
+
+@pytest.mark.parametrize("damp", [0, 8])
+def test_full_cycle_galilean(damp):
+    """The small beam-plasma workload with the Galilean update (and with
+    absorbing layers), three full cycles: every (mode, component) against the
+    oracle."""
+    wl = preset("small")
+    wl.galilean = True
+    wl.damp_cells = damp
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.step(3)
+    o.step(3)
+    for m in range(2):
+        errs = _component_errors(sim, o, m)
+        print("galilean small damp", damp, "mode", m, {k: f"{v[0]:.2e} ({v[1]:.1e})" for k, v in errs.items()})
+        _assert_components(errs, FIELD_TOL, m, **(REAL_STATE if damp else {}))
+
+
+def test_galilean_keeps_the_field_of_a_comoving_quiet_beam():
+    """A quiet gamma = 1000 beam moving with the window keeps its own field
+    under the Galilean cycle on the GPU (the oracle: 7e-7 after 20 steps, its
+    O(1/gamma^2) slip), and the lab-frame cycle does not (2.5e-3)."""
+    from workloads import quiet_beam
+    change = {}
+    for gal in (True, False):
+        b = quiet_beam("beam", 1000.0, 0.05, 128, 32, 0.05, 0.05, 3.2, 0.5, 0.2)
+        wl = Workload("beam", 128, 32, 2, 16, 0.05, 0.05, 0.05, 0.0, True, KPERP_JM_ZEROS, 1, [b], galilean=gal)
+        sim = _sim(wl)
+        E0 = np.stack([sim.get_field(0, c) for c in ("E+", "E-", "Ez")])
+        sim.step(20)
+        E1 = np.stack([sim.get_field(0, c) for c in ("E+", "E-", "Ez")])
+        change[gal] = np.linalg.norm(E1 - E0) / np.linalg.norm(E0)
+    print("field change after 20 steps", change)
+    assert change[True] < 1e-5
+    assert change[False] > 1e-3
+
+
+def test_fp16_split_overflow_is_reported():
+    """An operand beyond FP16 range (65504) in the FP16x3 Hankel products
+    gives inf; the library flags it and the next synchronizing call returns
+    PIC_ENUMERIC instead of handing back a field of infinities unannounced.
+    Vacuum grid, sources set from the host (no particles); the same sources
+    at FP32 are fine."""
+    from paper_1611_05712_amd import PicError
+    from paper_1611_05712_amd.pic import PIC_ENUMERIC
+    wl = _vacuum(128, 64, 16)
+    F = _random_fields(wl, seed=5)
+    F[:, 10] *= 1e7                  # rho^{n+1}: far beyond FP16 after the z-FFT
+    for prec, bad in ((0, False), (2, True)):
+        sim = _sim(wl, hankel_prec=prec)
+        for m in range(2):
+            for c in range(11):
+                sim.set_field(m, c, F[m, c])
+        sim.spectral_push()
+        if bad:
+            with pytest.raises(PicError) as e:
+                sim.get_field(0, "E+")
+            assert e.value.code == PIC_ENUMERIC
+        else:
+            assert np.isfinite(sim.get_field(0, "E+")).all()

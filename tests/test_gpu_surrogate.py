@@ -13,7 +13,7 @@ from workloads import mlp_layer_sizes, mlp_init, minibatch_indices
 pytestmark = pytest.mark.gpu
 
 DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1611_05712_amd",
-                    "data", "ncr_scan_s1_t64.json")
+                    "data", "ncr_scan_s1_t288.json")
 
 
 def _split(scan):

@@ -91,6 +91,8 @@ class Workload:
     species: List[Species]
     n0_m3: float = 1e23
     filter: int = 0          # binomial J / rho smoothing passes before the field update (0 or 1)
+    damp_cells: int = 0      # absorbing layer width at each z end (0: none)
+    galilean: bool = False   # Galilean field update in coordinates moving with the window
 
     @property
     def n_mobile(self) -> int:
@@ -151,6 +153,29 @@ def gaussian_bunch(n: int, charge_C: float, gamma: float, sigma_r: float, sigma_
         "ux": np.zeros(n, np.float32), "uy": np.zeros(n, np.float32),
         "uz": np.full(n, uz, np.float32), "w": np.full(n, w, np.float32),
     }
+
+
+def quiet_beam(name: str, gamma: float, total_weight: float, nz: int, nr: int, dz: float, dr: float,
+               zc: float, sigma_z: float, sigma_r: float, ppc=(2, 2, 4), q: float = -1.0) -> "Species":
+    """A cold beam without shot noise: particles on the regular 2x2x4 lattice of
+    the grid's cells, weights following a Gaussian profile (times r, the ring
+    volume), all moving along z with the same gamma; lattice points whose
+    weight is below 1e-6 of the largest are left out."""
+    pz, pr, pt = ppc
+    j, a, i, b, l = np.meshgrid(np.arange(nz), np.arange(pz), np.arange(nr), np.arange(pr), np.arange(pt),
+                                indexing="ij")
+    z = ((j + (a + 0.5) / pz) * dz).ravel()
+    r = ((i + (b + 0.5) / pr) * dr).ravel()
+    th = (2.0 * np.pi * (l + 0.5) / pt).ravel()
+    w = np.exp(-0.5 * ((z - zc) / sigma_z) ** 2 - 0.5 * (r / sigma_r) ** 2) * r
+    keep = w > 1e-6 * w.max()
+    z, r, th, w = z[keep], r[keep], th[keep], w[keep]
+    w = (w / w.sum() * total_weight).astype(np.float32)
+    n = z.size
+    uz = np.full(n, np.sqrt(gamma ** 2 - 1.0), np.float32)
+    zero = np.zeros(n, np.float32)
+    return Species(name, q, 1.0, True, r * np.cos(th), r * np.sin(th), z, zero, zero.copy(), uz, w, diag=True,
+                   self_field=True)
 
 
 def _plasma_species(nz, nr, dz, dr, zmin, ppc=(2, 2, 4)):
