@@ -354,7 +354,7 @@ int pic_timing_read(pic_ctx* ctx, int timer, double* total_ms, int64_t* launches
 
 /* Launch parameters that change speed only (results agree to rounding). */
 typedef struct {
-  int32_t gemm_tile_m;     /* output rows per Hankel-product workgroup tile: 32 or 64
+  int32_t gemm_tile_m;     /* output rows per Hankel-product workgroup tile: 32, 64 or 128
                               (must divide nr) */
   int32_t deposit_chunk;   /* particles per deposit work item of a dense tile: 2048, 4096
                               or 8192 (tiles above 3x this are cut into such chunks) */

@@ -86,6 +86,7 @@ class OracleSim:
         self.filter = int(getattr(wl, "filter", 0))
         self.damp = int(getattr(wl, "damp_cells", 0))
         self.galilean = bool(getattr(wl, "galilean", False))
+        self.shape = int(getattr(wl, "shape_order", 1))
         self.n_shift = 0
         self.hankel = [sp.HankelPair(m, wl.nr, wl.dr, wl.kperp_grid) for m in range(self.M)]
         self.kzm = sp.kz_modified(sp.kz_grid(wl.nz, wl.dz), wl.dz, wl.order)[None, :]
@@ -151,7 +152,8 @@ class OracleSim:
         self._real_pending = True
 
     def grid(self):
-        return {"nz": self.nz, "nr": self.nr, "dz": self.dz, "dr": self.dr, "zmin": self.zmin}
+        return {"nz": self.nz, "nr": self.nr, "dz": self.dz, "dr": self.dr, "zmin": self.zmin,
+                "shape": self.shape}
 
     # -- stage 1: gather + push -------------------------------------------
     def gather_push(self):

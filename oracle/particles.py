@@ -5,10 +5,12 @@ injection.
 The paper treats the particle coupling as standard PIC; the shape order, the
 treatment of the axis and the pusher are this implementation's readings:
   * linear (cloud-in-cell) shapes in z (periodic) and r, nodes at
-    z_j = zmin + j dz and r_i = (i + 1/2) dr;
-  * a particle below the first radial node shares weight with a ghost node
-    at r = -dr/2, which stands for node 0 seen across the axis; a component
-    of Hankel order nu takes the factor (-1)^nu there;
+    z_j = zmin + j dz and r_i = (i + 1/2) dr; or, as an option, cubic
+    B-spline shapes over the four nearest nodes along each axis;
+  * a particle below the first radial node shares weight with ghost nodes
+    at r = -dr/2 (and -3dr/2 for cubic shapes), which stand for nodes 0 (and
+    1) seen across the axis; a component of Hankel order nu takes the factor
+    (-1)^nu there;
   * nodes at i >= Nr are outside the box and dropped;
   * mode-m densities use the phase exp(i m theta_p) (the conjugate of the
     exp(-i m theta) field decomposition), divided by the ring volume
@@ -27,9 +29,21 @@ def _phase(x, y):
     return np.where(r > 0.0, (x + 1j * y) / safe, 1.0 + 0j), r
 
 
-def shape_nodes(z, r, zmin, dz, dr, nz):
-    """The four (j, i, weight) nodes of each particle's linear shape.
-    i may be -1 (ghost across the axis) or >= Nr (outside); j is wrapped."""
+def bspline_weights(f, order):
+    """(offset, weight) of the nodes of a particle at fractional position f in
+    [0, 1) past node 0: linear, nodes 0 and 1; cubic B-spline (the fourfold
+    convolution of the unit box), nodes -1 .. 2."""
+    if order == 1:
+        return ((0, 1.0 - f), (1, f))
+    g = 1.0 - f
+    return ((-1, g ** 3 / 6.0), (0, (4.0 - 6.0 * f ** 2 + 3.0 * f ** 3) / 6.0),
+            (1, (4.0 - 6.0 * g ** 2 + 3.0 * g ** 3) / 6.0), (2, f ** 3 / 6.0))
+
+
+def shape_nodes(z, r, zmin, dz, dr, nz, order=1):
+    """The (j, i, weight) nodes of each particle's shape (order 1: linear, 4
+    nodes; 3: cubic, 16).  i may be negative (ghosts across the axis) or
+    >= Nr (outside); j is wrapped."""
     sz = (z - zmin) / dz
     j0 = np.floor(sz)
     fz = sz - j0
@@ -39,8 +53,8 @@ def shape_nodes(z, r, zmin, dz, dr, nz):
     fr = sr - i0
     i0 = i0.astype(np.int64)
     nodes = []
-    for dj, wz in ((0, 1.0 - fz), (1, fz)):
-        for di, wr in ((0, 1.0 - fr), (1, fr)):
+    for dj, wz in bspline_weights(fz, order):
+        for di, wr in bspline_weights(fr, order):
             nodes.append(((j0 + dj) % nz, i0 + di, wz * wr))
     return nodes
 
@@ -49,14 +63,15 @@ def ring_volume(nr, dr, dz):
     return 2.0 * np.pi * (np.arange(nr) + 0.5) * dr * dr * dz
 
 
-def deposit_scalar(val, nu, z, r, zmin, dz, dr, nz, nr):
+def deposit_scalar(val, nu, z, r, zmin, dz, dr, nz, nr, order=1):
     """Deposit a complex per-particle quantity of Hankel order nu onto the
     [Nr, Nz] grid (a density: divided by the ring volume)."""
     acc = np.zeros(nr * nz, dtype=np.complex128)
     sgn = -1.0 if (nu % 2) else 1.0
-    for j, i, wgt in shape_nodes(z, r, zmin, dz, dr, nz):
-        fold = np.where(i == -1, sgn, 1.0)
-        ii = np.where(i == -1, 0, i)
+    for j, i, wgt in shape_nodes(z, r, zmin, dz, dr, nz, order):
+        # ghost node -1 - i' stands for node i' across the axis
+        fold = np.where(i < 0, sgn, 1.0)
+        ii = np.where(i < 0, -1 - i, i)
         keep = ii < nr
         idx = ii[keep] * nz + j[keep]
         v = (wgt * fold * val)[keep]
@@ -71,7 +86,7 @@ def deposit_rho(n_modes, qw, x, y, z, grid):
     out = np.zeros((n_modes, grid["nr"], grid["nz"]), dtype=np.complex128)
     for m in range(n_modes):
         out[m] = deposit_scalar(qw * ph ** m, m, z, r, grid["zmin"], grid["dz"],
-                                grid["dr"], grid["nz"], grid["nr"])
+                                grid["dr"], grid["nz"], grid["nr"], grid.get("shape", 1))
     return out
 
 
@@ -82,7 +97,7 @@ def deposit_current(n_modes, qw, x, y, z, vx, vy, vz, grid):
     (v_x + i v_y) exp(i (m-1) theta)/2; J_z takes v_z exp(i m theta)."""
     ph, r = _phase(x, y)
     out = np.zeros((n_modes, 3, grid["nr"], grid["nz"]), dtype=np.complex128)
-    args = (z, r, grid["zmin"], grid["dz"], grid["dr"], grid["nz"], grid["nr"])
+    args = (z, r, grid["zmin"], grid["dz"], grid["dr"], grid["nz"], grid["nr"], grid.get("shape", 1))
     for m in range(n_modes):
         out[m, 0] = deposit_scalar(qw * (vx - 1j * vy) / 2.0 * ph ** (m + 1), m + 1, *args)
         out[m, 1] = deposit_scalar(qw * (vx + 1j * vy) / 2.0 * ph ** (m - 1), m - 1, *args)
@@ -94,8 +109,8 @@ def gather_scalar(F, nu, nodes, nr):
     sgn = -1.0 if (nu % 2) else 1.0
     out = 0.0
     for j, i, wgt in nodes:
-        fold = np.where(i == -1, sgn, 1.0)
-        ii = np.where(i == -1, 0, i)
+        fold = np.where(i < 0, sgn, 1.0)
+        ii = np.where(i < 0, -1 - i, i)
         keep = ii < nr
         iic = np.where(keep, ii, 0)
         out = out + np.where(keep, wgt * fold * F[iic, j], 0.0)
@@ -110,7 +125,7 @@ def gather_cartesian(Fm, x, y, z, grid):
                        + sum_{m>=1} conj(F_{+,m}) exp(i (m+1) theta) ]
     using F_{-,-m} = conj(F_{+,m})."""
     ph, r = _phase(x, y)
-    nodes = shape_nodes(z, r, grid["zmin"], grid["dz"], grid["dr"], grid["nz"])
+    nodes = shape_nodes(z, r, grid["zmin"], grid["dz"], grid["dr"], grid["nz"], grid.get("shape", 1))
     nr = grid["nr"]
     fz = np.zeros(x.shape, dtype=np.float64)
     fxy = np.zeros(x.shape, dtype=np.complex128)

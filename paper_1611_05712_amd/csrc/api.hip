@@ -1114,7 +1114,7 @@ int pic_get_tuning(pic_ctx* x, pic_tuning* t) {
 
 int pic_set_tuning(pic_ctx* x, const pic_tuning* t) {
   if (!x || !t) return PIC_EINVAL;
-  if (t->gemm_tile_m != 32 && t->gemm_tile_m != 64) return PIC_EINVAL;
+  if (t->gemm_tile_m != 32 && t->gemm_tile_m != 64 && t->gemm_tile_m != 128) return PIC_EINVAL;
   if (t->deposit_chunk != 2048 && t->deposit_chunk != 4096 && t->deposit_chunk != 8192) return PIC_EINVAL;
   if ((x->nr % t->gemm_tile_m) != 0) return PIC_EINVAL;
   x->gemm_bm = t->gemm_tile_m / 32;
@@ -1428,9 +1428,9 @@ int pic_autotune(pic_ctx* x, int steps_per_trial, pic_tuning* best, double* best
     (void)hipEventDestroy(a);
     return PIC_EHIP;
   }
-  pic_tuning cand[6];
+  pic_tuning cand[9];
   int nc = 0;
-  for (int tm : {64, 32})
+  for (int tm : {64, 128, 32})
     for (int ch : {2048, 4096, 8192})
       if (x->nr % tm == 0) cand[nc++] = pic_tuning{tm, ch};
   int rc = PIC_OK;

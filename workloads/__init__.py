@@ -93,6 +93,7 @@ class Workload:
     filter: int = 0          # binomial J / rho smoothing passes before the field update (0 or 1)
     damp_cells: int = 0      # absorbing layer width at each z end (0: none)
     galilean: bool = False   # Galilean field update in coordinates moving with the window
+    shape_order: int = 1     # particle shape: 1 linear, 3 cubic B-spline
 
     @property
     def n_mobile(self) -> int:
