@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--hankel-prec", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--damp-cells", type=int, default=0, metavar="N",
                     help="variant: absorbing layers of N cells at both z ends (not the headline line)")
+    ap.add_argument("--shape-order", type=int, default=1, choices=[1, 3],
+                    help="variant: particle shape (3: cubic B-spline), not the headline line")
     ap.add_argument("--galilean", action="store_true",
                     help="variant: Galilean field update in coordinates moving with the window (not the headline line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -267,6 +269,7 @@ def main():
     wl = preset(args.workload)
     wl.damp_cells = args.damp_cells
     wl.galilean = args.galilean
+    wl.shape_order = args.shape_order
     sim = Simulation.from_workload(wl, hankel_prec=prec, device="cuda:0")
     t0 = time.perf_counter()
     (sim.step if args.eager else sim.step_graph)(args.warmup)
@@ -332,7 +335,7 @@ def main():
                    "mobile_particles": int(n_part), "cells_per_mode": wl.nz * wl.nr,
                    "modes": wl.n_modes, "order": wl.order,
                    "hankel_prec": args.hankel_prec, "positions": "f64", "damp_cells": args.damp_cells,
-                   "galilean": args.galilean,
+                   "galilean": args.galilean, "shape_order": args.shape_order,
                    "stepping": "eager" if args.eager else "hip graph, two steps per replay"},
         "field_cell_updates_per_s": cells * args.steps / (spectral_ms / 1e3) if spectral_ms else None,
         "roofline": roofline,

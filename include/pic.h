@@ -130,6 +130,12 @@ typedef struct {
                                  periodic one- and half-node moves; the half move is zero at the
                                  z Nyquist wavenumber) and E, B are not shifted by the window
                                  move.  0 (default): the lab-frame update of Eqs. (1a)-(1b) */
+  int32_t shape_order;        /* particle shape of the deposit and the gather: 1 (or 0, the
+                                 default) linear; 3 cubic B-spline over the four nearest nodes
+                                 along z and along r (ghost nodes at -dr/2 and -3dr/2 stand for
+                                 nodes 0 and 1 across the axis with the factor (-1)^nu of the
+                                 Hankel order).  Cubic shapes deposit every particle straight
+                                 into the tile blocks (no register runs): a slower option */
 } pic_config;
 
 typedef struct {

@@ -171,6 +171,7 @@ int validate(const pic_config* c, const pic_species* s, int ns) {
   if (c->filter < 0 || c->filter > 4) return PIC_EINVAL;
   if (c->damp_cells < 0 || c->damp_cells > c->nz / 4) return PIC_EINVAL;
   if (c->galilean != 0 && (c->galilean != 1 || !c->moving_window)) return PIC_EINVAL;
+  if (c->shape_order != 0 && c->shape_order != 1 && c->shape_order != 3) return PIC_EINVAL;
   if (ns < 0 || ns > kMaxSpecies || (ns > 0 && !s)) return PIC_EINVAL;
   for (int i = 0; i < ns; ++i) {
     const pic_species& p = s[i];
@@ -209,10 +210,15 @@ int64_t capacity_for(const pic_config* c, const pic_species* s, int ns, int64_t 
 // Lays out (or measures) the workspace.
 int halo_cells(double dt, double d) { return std::max(1, (int)ceil(dt / d - 1e-12)); }
 
+// halo of the deposit's tile blocks: the cells a particle moves per step, plus
+// one for the wider cubic shape
+int deposit_halo(const pic_config* c) {
+  return std::max(halo_cells(c->dt, c->dz), halo_cells(c->dt, c->dr)) + (c->shape_order == 3 ? 1 : 0);
+}
+
 size_t carve(pic_ctx* x, char* base, const pic_config* c, int64_t cap) {
   Carver cv;
-  const DepositShape dep = deposit_shape(c->nz, c->nr, c->n_modes,
-                                         std::max(halo_cells(c->dt, c->dz), halo_cells(c->dt, c->dr)), cap);
+  const DepositShape dep = deposit_shape(c->nz, c->nr, c->n_modes, deposit_halo(c), cap);
   cv.base = base;
   const int M = c->n_modes, nz = c->nz, nr = c->nr;
   const size_t plane = (size_t)nr * nz;
@@ -462,9 +468,7 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
   if (cnt.mobile > cap) return PIC_ENOSPC;
   {
     // the deposit's FP64 tile block must fit one workgroup's LDS
-    const DepositShape dep = deposit_shape(cfg->nz, cfg->nr, cfg->n_modes,
-                                           std::max(halo_cells(cfg->dt, cfg->dz), halo_cells(cfg->dt, cfg->dr)),
-                                           cap);
+    const DepositShape dep = deposit_shape(cfg->nz, cfg->nr, cfg->n_modes, deposit_halo(cfg), cap);
     int dev = 0, lds_max = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -498,6 +502,7 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
   g.inv_dr = 1.0 / cfg->dr;
   g.zmin0 = cfg->z_min;
   g.moving_window = cfg->moving_window;
+  g.shape = cfg->shape_order == 3 ? 3 : 1;
   x->hz = halo_cells(cfg->dt, cfg->dz);
   x->hr = halo_cells(cfg->dt, cfg->dr);
   x->gemm_bm = 2;

@@ -40,6 +40,7 @@ struct Grid {
   double inv_dz, inv_dr;
   double zmin0;
   int moving_window;
+  int shape;            // particle shape order: 1 linear, 3 cubic B-spline
 };
 
 // Particle storage (structure of arrays); w holds the signed charge weight q*w.

@@ -239,6 +239,51 @@ __device__ __forceinline__ uint32_t pos_key(const ShapePos& s, int nr) {
   return (uint32_t)s.j0 * 2048u + (uint32_t)ic;
 }
 
+// Cubic B-spline shape (an option): the four nodes -1 .. 2 of each axis around
+// the cell start, weights of the fourfold convolution of the unit box.
+__device__ __forceinline__ void cubic_weights(float f, float (&w)[4]) {
+  const float g = 1.f - f;
+  w[0] = g * g * g * (1.f / 6.f);
+  w[1] = (4.f - 6.f * f * f + 3.f * f * f * f) * (1.f / 6.f);
+  w[2] = (4.f - 6.f * g * g + 3.f * g * g * g) * (1.f / 6.f);
+  w[3] = f * f * f * (1.f / 6.f);
+}
+
+// One particle's K values on its 16 cubic nodes, straight into the FP64 block
+// (no register runs: sixteen nodes per value would not fit).  Ghost nodes
+// -1, -2 across the axis stand for nodes 0, 1 with the factor (-1)^nu of each
+// value's Hankel order; nodes at i >= nr are dropped; rows outside the block
+// (corrupted positions only) are skipped.
+template <int TR, int H, int K, class Set, class OffFn>
+__device__ __forceinline__ void cubic_deposit(double* __restrict__ lds, const float (&v)[K], const ShapePos& s,
+                                              const Grid& g, int J0, int C0, OffFn off) {
+  using B = Blk<TR, H>;
+  float wz[4], wr[4];
+  cubic_weights(s.fz, wz);
+  cubic_weights(s.fr, wr);
+  int bz0 = s.j0 - 1 - (J0 - H);
+  if (bz0 < 0) bz0 += g.nz;
+  if (bz0 >= g.nz) bz0 -= g.nz;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int i = s.i0 - 1 + a;
+    const bool ghost = i < 0;
+    if (ghost) i = -1 - i;
+    const int br = i - (C0 - 1 - H);
+    if (i >= g.nr || br < 0 || br >= B::BR) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int bz = bz0 + b;
+      if (bz < 0 || bz >= B::BZ) continue;
+      const int node = br * B::BZ + bz;
+      const float w = wr[a] * wz[b];
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        atomicAdd(lds + off(k) + node, (double)((ghost && Set::parity(k) ? -w : w) * v[k]));
+    }
+  }
+}
+
 // Register accumulator of one position kind: the cell key it belongs to and
 // the K values times the four node weights (ia,j0), (ia,j0+1), (ib,j0),
 // (ib,j0+1).  A run adds at most a few particles before it is flushed into
@@ -399,7 +444,7 @@ enum DepMode { kDepFull = 0, kDepCarry = 1, kDepEdgeRho = 2, kDepIon = 3 };
 
 // Otherwise the first work item of each tile adds the tile's FP64 background
 // block `ionblk` (when given) to the densities it deposits.
-template <int TR, int H, int M, int MODE>
+template <int TR, int H, int M, int MODE, int SHAPE>
 __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict__ offset,
                                                  const int* __restrict__ nchunk, const int* __restrict__ chunk_start,
                                                  float* __restrict__ scratch, const double* __restrict__ ionblk, Grid g,
@@ -576,6 +621,29 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
         const bool cold = __ballot(valid && (ux != 0.f || uy != 0.f || uz != 0.f)) == 0;
         const float ginv = 1.f / sqrtf(1.f + ux * ux + uy * uy + uz * uz);
         const float vx = ux * ginv, vy = uy * ginv, vz = uz * ginv;
+        if constexpr (SHAPE == 3) {
+          // cubic shapes: every position of the particle straight into the block
+          if (valid) {
+            if (kRho1J) {
+              const ShapePos s = shape_at(x, y, z, zmin, g);
+              float v[RS::K];
+              RS::values(qw, s.eith, v);
+              cubic_deposit<TR, H, RS::K, RS>(lds, v, s, g, J0, C0, [](int k) { return RS::off(4, k); });
+              const ShapePos sh = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy,
+                                           z - 0.5 * dt * (double)vz, zmin, g);
+              float vj[JS::K];
+              JS::values(qw, vx, vy, vz, sh.eith, vj);
+              cubic_deposit<TR, H, JS::K, JS>(lds, vj, sh, g, J0, C0, [](int k) { return JS::off(k); });
+            }
+            if (kRhoN) {
+              const ShapePos s0 = shape_at(x - dt * (double)vx, y - dt * (double)vy, z - dt * (double)vz, zmin, g);
+              float v[RS::K];
+              RS::values(qw, s0.eith, v);
+              cubic_deposit<TR, H, RS::K, RS>(lds, v, s0, g, J0, C0, [](int k) { return RS::off(3, k); });
+            }
+          }
+          continue;
+        }
         // rho^{n+1} at x^{n+1}, in the run's cell (particles beyond the last
         // radial node share the last key column and deposit nothing); rho^n
         // too when the whole wave is at rest
@@ -835,7 +903,7 @@ static bool set_lds_limit(K kernel, size_t bytes) {
          hipSuccess;
 }
 
-template <int TR, int H, int M>
+template <int TR, int H, int M, int SHAPE>
 static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chunk_start, float2* scratch,
                        float2* real, const double* ionblk, double* ionblk_out, const Grid& g, const DepositShape& d,
                        DevState* st, int stages, int rho_mode, hipStream_t s) {
@@ -854,10 +922,10 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
     if (!(stages & kDepTiles)) return;
     static bool attr_ion = false;
     if (!attr_ion) {
-      if (!set_lds_limit(k_deposit<TR, H, M, kDepIon>, lds)) return;   // error stays pending for the caller's check
+      if (!set_lds_limit(k_deposit<TR, H, M, kDepIon, SHAPE>, lds)) return;   // error stays pending for the caller's check
       attr_ion = true;
     }
-    hipLaunchKernelGGL((k_deposit<TR, H, M, kDepIon>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
+    hipLaunchKernelGGL((k_deposit<TR, H, M, kDepIon, SHAPE>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
                        chunk_start, (float*)scratch, (const double*)nullptr, g, tg, st);
     const int64_t n = (int64_t)d.ntiles * RhoVals<M>::N * Blk<TR, H>::NODES;
     hipLaunchKernelGGL((k_ion_reduce<TR, H, M>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nchunk,
@@ -867,19 +935,19 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
   if (stages & kDepTiles) {
     static bool attr_set[3] = {false, false, false};   // dynamic LDS above the default limit
     if (!attr_set[0]) {
-      if (!set_lds_limit(k_deposit<TR, H, M, kDepFull>, lds) || !set_lds_limit(k_deposit<TR, H, M, kDepCarry>, lds) ||
-          !set_lds_limit(k_deposit<TR, H, M, kDepEdgeRho>, lds))
+      if (!set_lds_limit(k_deposit<TR, H, M, kDepFull, SHAPE>, lds) || !set_lds_limit(k_deposit<TR, H, M, kDepCarry, SHAPE>, lds) ||
+          !set_lds_limit(k_deposit<TR, H, M, kDepEdgeRho, SHAPE>, lds))
         return;
       attr_set[0] = true;
     }
     if (rho_mode == kRhoDeposit) {
-      hipLaunchKernelGGL((k_deposit<TR, H, M, kDepFull>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
+      hipLaunchKernelGGL((k_deposit<TR, H, M, kDepFull, SHAPE>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
                          chunk_start, (float*)scratch, ionblk, g, tg, st);
     } else {
-      hipLaunchKernelGGL((k_deposit<TR, H, M, kDepCarry>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
+      hipLaunchKernelGGL((k_deposit<TR, H, M, kDepCarry, SHAPE>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
                          chunk_start, (float*)scratch, ionblk, g, tg, st);
       if (rho_mode == kRhoCarryShift)
-        hipLaunchKernelGGL((k_deposit<TR, H, M, kDepEdgeRho>), dim3(2 * d.ntr), dim3(256), lds, s, p, offset, nchunk,
+        hipLaunchKernelGGL((k_deposit<TR, H, M, kDepEdgeRho, SHAPE>), dim3(2 * d.ntr), dim3(256), lds, s, p, offset, nchunk,
                            chunk_start, (float*)scratch, ionblk, g, tg, st);
     }
   }
@@ -895,23 +963,29 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
   }
 }
 
-template <int H>
+template <int H, int SHAPE>
 static void launch_dep_h(const Parts& p, const int* offset, int* nchunk, int* chunk_start, float2* scratch,
                          float2* real, const double* ionblk, double* ionblk_out, const Grid& g, const DepositShape& d,
                          DevState* st, int stages, int rho_mode, hipStream_t s) {
   switch (g.nmodes) {
-    case 1: launch_dep<16, H, 1>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
-    case 2: launch_dep<8, H, 2>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
-    case 3: launch_dep<8, H, 3>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
-    default: launch_dep<8, H, 4>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
+    case 1: launch_dep<16, H, 1, SHAPE>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
+    case 2: launch_dep<8, H, 2, SHAPE>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
+    case 3: launch_dep<8, H, 3, SHAPE>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
+    default: launch_dep<8, H, 4, SHAPE>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s); break;
   }
 }
 
 void launch_deposit(const Parts& p, const int* offset, const DepositShape& d, int* nchunk, int* chunk_start,
                     float2* scratch, float2* real, const double* ionblk, double* ionblk_out, const Grid& g,
                     DevState* st, int stages, int rho_mode, hipStream_t s) {
-  if (d.halo == 1) launch_dep_h<1>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s);
-  else launch_dep_h<2>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s);
+  // the block halo: cells a particle moves per step (1 or 2), one more for cubic shapes
+  if (g.shape == 3) {
+    if (d.halo == 2) launch_dep_h<2, 3>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s);
+    else launch_dep_h<3, 3>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s);
+  } else {
+    if (d.halo == 1) launch_dep_h<1, 1>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s);
+    else launch_dep_h<2, 1>(p, offset, nchunk, chunk_start, scratch, real, ionblk, ionblk_out, g, d, st, stages, rho_mode, s);
+  }
 }
 
 }  // namespace pic

@@ -157,6 +157,44 @@ __device__ __forceinline__ void gather_eb(const float2* __restrict__ gf, const S
   cartesian<M>(a, 3, s.eith, Bx, By, Bz);
 }
 
+// Cubic B-spline gather (an option): the 4 x 4 nodes -1 .. 2 around the
+// cell start along z (periodic) and r; ghost nodes -1, -2 across the axis
+// read nodes 0, 1 with the factor (-1)^nu; nodes at i >= nr are outside.
+__device__ __forceinline__ void cubic_wts(float f, float (&w)[4]) {
+  const float g = 1.f - f;
+  w[0] = g * g * g * (1.f / 6.f);
+  w[1] = (4.f - 6.f * f * f + 3.f * f * f * f) * (1.f / 6.f);
+  w[2] = (4.f - 6.f * g * g + 3.f * g * g * g) * (1.f / 6.f);
+  w[3] = f * f * f * (1.f / 6.f);
+}
+
+template <int M>
+__device__ __forceinline__ void gather_eb_cubic(const float2* __restrict__ gf, const ShapePos& s, const Grid& g,
+                                                float& Ex, float& Ey, float& Ez, float& Bx, float& By, float& Bz) {
+  Gathered<M> a;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a.f[m][c] = make_float2(0.f, 0.f);
+  float wz[4], wr[4];
+  cubic_wts(s.fz, wz);
+  cubic_wts(s.fr, wr);
+  for (int q = 0; q < 4; ++q) {
+    int i = s.i0 - 1 + q;
+    const bool ghost = i < 0;
+    if (ghost) i = -1 - i;
+    if (i >= g.nr) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = (s.j0 - 1 + b) & (g.nz - 1);   // nz is a power of two
+      const float w = wr[q] * wz[b];
+      gather_node<M>(a, gf, i, j, g.nz, w, ghost ? -w : w);
+    }
+  }
+  cartesian<M>(a, 0, s.eith, Ex, Ey, Ez);
+  cartesian<M>(a, 3, s.eith, Bx, By, Bz);
+}
+
 // --------------------------------------------------------------------------
 // gather + Boris push + move + new cell key + key histogram.  Each thread
 // pushes kPushPer particles, blockDim apart, all their loads issued before any
@@ -172,14 +210,15 @@ struct PushRec {
   uint8_t sp;
 };
 
-template <int M>
+template <int M, int SHAPE>
 __device__ __forceinline__ uint32_t push_one(PushRec& r, const float2* __restrict__ gf, const Grid& g,
                                              const SpeciesConst& sc, double zmin, bool kill) {
   if (kill && r.z < zmin) return (uint32_t)g.ncells;
   const float qm = sc.qm[r.sp];
   ShapePos s = shape_at(r.x, r.y, r.z, zmin, g);
   float Ex, Ey, Ez, Bx, By, Bz;
-  gather_eb<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
+  if constexpr (SHAPE == 3) gather_eb_cubic<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
+  else gather_eb<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
   // Boris rotation (J. P. Boris, 1970).  The transverse momenta and all
   // increments are FP32; u_z accumulates its increments in FP64.
   float eps = qm * (float)g.dt * 0.5f;
@@ -206,7 +245,7 @@ __device__ __forceinline__ uint32_t push_one(PushRec& r, const float2* __restric
   return cell_key(shape_at(r.x, r.y, r.z, zmin, g), g);
 }
 
-template <int M>
+template <int M, int SHAPE>
 __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __restrict__ gf, Grid g, SpeciesConst sc,
                                                      const DevState* __restrict__ st, uint32_t* __restrict__ key,
                                                      int* __restrict__ count) {
@@ -240,7 +279,7 @@ __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __re
 #pragma unroll
   for (int q = 0; q < kPushPer; ++q) {
     k[q] = kInvalidKey;
-    if (base + q * 256 < n) k[q] = push_one<M>(r[q], gf, g, sc, zmin, kill);
+    if (base + q * 256 < n) k[q] = push_one<M, SHAPE>(r[q], gf, g, sc, zmin, kill);
   }
 #pragma unroll
   for (int q = 0; q < kPushPer; ++q) {
@@ -504,11 +543,20 @@ static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 void launch_gather_push(const Parts& p, const float2* gf, const Grid& g, const SpeciesConst& sc,
                         const DevState* st, uint32_t* key, int* count, int cap, hipStream_t s) {
   dim3 grid(nblk(cap, kPushPer * 256));
+  if (g.shape == 3) {
+    switch (g.nmodes) {
+      case 1: hipLaunchKernelGGL((k_gather_push<1, 3>), grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+      case 2: hipLaunchKernelGGL((k_gather_push<2, 3>), grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+      case 3: hipLaunchKernelGGL((k_gather_push<3, 3>), grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+      default: hipLaunchKernelGGL((k_gather_push<4, 3>), grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+    }
+    return;
+  }
   switch (g.nmodes) {
-    case 1: hipLaunchKernelGGL(k_gather_push<1>, grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
-    case 2: hipLaunchKernelGGL(k_gather_push<2>, grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
-    case 3: hipLaunchKernelGGL(k_gather_push<3>, grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
-    default: hipLaunchKernelGGL(k_gather_push<4>, grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+    case 1: hipLaunchKernelGGL((k_gather_push<1, 1>), grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+    case 2: hipLaunchKernelGGL((k_gather_push<2, 1>), grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+    case 3: hipLaunchKernelGGL((k_gather_push<3, 1>), grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
+    default: hipLaunchKernelGGL((k_gather_push<4, 1>), grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
   }
 }
 void launch_pack_gather(const float2* real, float2* gf, int nr, int nz, int M, hipStream_t s) {

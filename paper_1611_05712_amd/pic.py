@@ -48,7 +48,8 @@ class pic_config(ctypes.Structure):
                 ("dt", ctypes.c_double), ("z_min", ctypes.c_double),
                 ("moving_window", ctypes.c_int32), ("kperp_grid", ctypes.c_int32),
                 ("hankel_prec", ctypes.c_int32), ("current_correction", ctypes.c_int32),
-                ("filter", ctypes.c_int32), ("damp_cells", ctypes.c_int32), ("galilean", ctypes.c_int32)]
+                ("filter", ctypes.c_int32), ("damp_cells", ctypes.c_int32), ("galilean", ctypes.c_int32),
+                ("shape_order", ctypes.c_int32)]
 
 
 class pic_tuning(ctypes.Structure):
@@ -185,14 +186,14 @@ class Simulation:
     def __init__(self, nz, nr, n_modes, order, dz, dr, dt, z_min, species: Sequence,
                  moving_window=False, kperp_grid=KPERP_JM_ZEROS, hankel_prec=H_FP32,
                  current_correction=True, max_particles=0, device="cuda:0", stream=None, filter=0,
-                 damp_cells=0, galilean=False):
+                 damp_cells=0, galilean=False, shape_order=1):
         import torch
         L = load()
         self._L = L
         self.device = torch.device(device)
         self.cfg = pic_config(nz, nr, n_modes, order, dz, dr, dt, z_min, int(bool(moving_window)),
                               kperp_grid, hankel_prec, int(bool(current_correction)), int(filter),
-                              int(damp_cells), int(bool(galilean)))
+                              int(damp_cells), int(bool(galilean)), int(shape_order))
         self.nz, self.nr, self.n_modes = nz, nr, n_modes
         self.species_names = [s.name for s in species]
         self._keep = []
@@ -235,6 +236,7 @@ class Simulation:
         kw.setdefault("filter", getattr(wl, "filter", 0))
         kw.setdefault("damp_cells", getattr(wl, "damp_cells", 0))
         kw.setdefault("galilean", getattr(wl, "galilean", False))
+        kw.setdefault("shape_order", getattr(wl, "shape_order", 1))
         return cls(wl.nz, wl.nr, wl.n_modes, wl.order, wl.dz, wl.dr, wl.dt, wl.zmin, wl.species,
                    moving_window=wl.moving_window, kperp_grid=wl.kperp_grid, **kw)
 

@@ -238,3 +238,99 @@ def test_injected_lattice_has_the_plasma_density():
     np.testing.assert_allclose(rho[0][1:nr - 1, nz - 1].real, 0.5 * density, rtol=1e-6)
     np.testing.assert_allclose(rho[0][1:nr - 1, 0].real, 0.5 * density, rtol=1e-6)   # periodic wrap
     assert np.abs(rho[0][:, 1:nz - 1]).max() == 0.0
+
+
+# --- cubic B-spline shapes (an option of the deposit and gather) -------------
+def _bspline_cox_de_boor(x, k):
+    """Uniform B-spline of degree k on knots 0, 1, ..., k+1, by the textbook
+    Cox-de Boor recursion (independent of the closed forms in the oracle)."""
+    if k == 0:
+        return np.where((x >= 0.0) & (x < 1.0), 1.0, 0.0)
+    return (x * _bspline_cox_de_boor(x, k - 1) + (k + 1 - x) * _bspline_cox_de_boor(x - 1.0, k - 1)) / k
+
+
+def test_cubic_weights_are_the_cubic_bspline():
+    # node at offset d from the particle's cell start gets B3 centred on the
+    # particle: B3(d - f + 2) with B3 the degree-3 spline on knots 0..4
+    f = np.linspace(0.0, 0.999, 37)
+    for d, w in pt.bspline_weights(f, 3):
+        np.testing.assert_allclose(w, _bspline_cox_de_boor(d - f + 2.0, 3), atol=1e-15)
+    # and the linear ones are the degree-1 spline
+    for d, w in pt.bspline_weights(f, 1):
+        np.testing.assert_allclose(w, _bspline_cox_de_boor(d - f + 1.0, 1), atol=1e-15)
+
+
+def test_cubic_weight_moments():
+    # partition of unity, centred (first moment 0), variance 1/3 cell^2 (four
+    # unit boxes convolved: 4 x 1/12)
+    f = np.random.default_rng(3).uniform(0.0, 1.0, 1000)
+    ws = pt.bspline_weights(f, 3)
+    m0 = sum(w for _, w in ws)
+    m1 = sum(w * (d - f) for d, w in ws)
+    m2 = sum(w * (d - f) ** 2 for d, w in ws)
+    np.testing.assert_allclose(m0, 1.0, atol=1e-14)
+    np.testing.assert_allclose(m1, 0.0, atol=1e-14)
+    np.testing.assert_allclose(m2, 1.0 / 3.0, atol=1e-14)
+
+
+CUBIC = dict(GRID, shape=3)
+
+
+@pytest.mark.parametrize("nu", [-1, 0, 1, 2, 3])
+def test_cubic_deposit_is_the_adjoint_of_the_gather(nu):
+    # the same adjointness as for linear shapes, with the cubic shape and its
+    # two ghost nodes across the axis (r = -dr/2 -> node 0, -3dr/2 -> node 1)
+    x, y, z, r = _axis_particles(400, seed=31 + nu)
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal(x.size) + 1j * rng.standard_normal(x.size)
+    F = rng.standard_normal((GRID["nr"], GRID["nz"])) + 1j * rng.standard_normal((GRID["nr"], GRID["nz"]))
+    rho = pt.deposit_scalar(a, nu, z, r, GRID["zmin"], GRID["dz"], GRID["dr"], GRID["nz"], GRID["nr"], 3)
+    lhs = (_vol()[:, None] * rho * F).sum()
+    nodes = pt.shape_nodes(z, r, GRID["zmin"], GRID["dz"], GRID["dr"], GRID["nz"], 3)
+    rhs = (a * pt.gather_scalar(F, nu, nodes, GRID["nr"])).sum()
+    assert abs(lhs - rhs) < 1e-12 * abs(rhs)
+
+
+def test_cubic_gather_of_polynomials_in_z():
+    # a cubic B-spline reproduces linear functions exactly and smooths a
+    # quadratic by its variance: the gather of z^2 is z^2 + dz^2 / 3
+    rng = np.random.default_rng(5)
+    n = 300
+    zs = rng.uniform(0.3, 0.7, n) * GRID["nz"] * GRID["dz"] + GRID["zmin"]
+    rs = rng.uniform(3.0, 6.0, n) * GRID["dr"]            # away from axis and edge
+    zj = GRID["zmin"] + np.arange(GRID["nz"]) * GRID["dz"]
+    nodes = pt.shape_nodes(zs, rs, GRID["zmin"], GRID["dz"], GRID["dr"], GRID["nz"], 3)
+    lin = np.tile(2.0 * zj - 0.3, (GRID["nr"], 1)).astype(complex)
+    quad = np.tile(zj ** 2, (GRID["nr"], 1)).astype(complex)
+    np.testing.assert_allclose(pt.gather_scalar(lin, 0, nodes, GRID["nr"]).real, 2.0 * zs - 0.3, atol=1e-12)
+    np.testing.assert_allclose(pt.gather_scalar(quad, 0, nodes, GRID["nr"]).real,
+                               zs ** 2 + GRID["dz"] ** 2 / 3.0, atol=1e-12)
+
+
+def test_cubic_single_particle_charge_and_mode_phase():
+    # an interior particle puts its whole charge on 16 nodes, with the mode
+    # phase e^{i m theta}
+    th = 0.9
+    rp, zp = 2.37 * GRID["dr"], GRID["zmin"] + 5.61 * GRID["dz"]
+    x, y = np.array([rp * np.cos(th)]), np.array([rp * np.sin(th)])
+    rho = pt.deposit_rho(3, np.array([1.0]), x, y, np.array([zp]), CUBIC)
+    for m in range(3):
+        q = (rho[m] * _vol()[:, None]).sum()
+        np.testing.assert_allclose(q, np.exp(1j * m * th), atol=1e-13)
+        assert np.count_nonzero(np.abs(rho[m]) > 0) == 16
+
+
+def test_cubic_gather_through_the_axis():
+    # near the axis the cubic shape reaches both ghost nodes (-dr/2 and -3dr/2);
+    # standing for nodes 0 and 1 with the factor (-1)^nu they continue an even
+    # field (nu = 0) evenly and an odd one (nu = 1) oddly across r = 0, so the
+    # spline still reproduces polynomials: r^2 -> s^2 + dr^2/3, r -> s
+    s = np.random.default_rng(8).uniform(0.0, 2.0, 200) * GRID["dr"]
+    z = np.full(s.size, GRID["zmin"] + 7.3 * GRID["dz"])
+    ri = (np.arange(GRID["nr"]) + 0.5) * GRID["dr"]
+    nodes = pt.shape_nodes(z, s, GRID["zmin"], GRID["dz"], GRID["dr"], GRID["nz"], 3)
+    even = np.tile((ri ** 2)[:, None], (1, GRID["nz"])).astype(complex)
+    odd = np.tile(ri[:, None], (1, GRID["nz"])).astype(complex)
+    np.testing.assert_allclose(pt.gather_scalar(even, 0, nodes, GRID["nr"]).real, s ** 2 + GRID["dr"] ** 2 / 3.0,
+                               atol=1e-12)
+    np.testing.assert_allclose(pt.gather_scalar(odd, 1, nodes, GRID["nr"]).real, s, atol=1e-12)
