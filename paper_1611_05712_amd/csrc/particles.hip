@@ -57,26 +57,37 @@ __device__ __forceinline__ void wave_count(uint32_t k, int* __restrict__ count) 
 
 // --------------------------------------------------------------------------
 // field gather.  The gather reads a node-interleaved copy of the real-space
-// E, B: record (i, j) holds, for m = 0..M-1, E+, E-, Ez, B+, B-, Bz of mode m
-// (6M complex float32, 16-byte aligned), so a particle's four nodes are two
-// contiguous segments [(ia, j0), (ia, j0+1)] and [(ib, j0), (ib, j0+1)].
+// E, B: record (i, j) holds what the Cartesian field at a particle needs, so a
+// particle's four nodes are two contiguous segments [(ia, j0), (ia, j0+1)] and
+// [(ib, j0), (ib, j0+1)].  Mode 0 is real (F_+,0 = conj F_-,0, F_z,0 real):
+// its part is E-, B- and the real parts of Ez, Bz (4 float2 with one of
+// padding); every mode m >= 1 adds E+, E-, Ez, B+, B-, Bz.  kRecF2(M) = 6M - 2
+// float2 per record, an even count, so records stay 16-byte aligned.
 // --------------------------------------------------------------------------
 // A workgroup packs 256 consecutive nodes: the 6M planes are read coalesced
 // into the node records in LDS, which are then written out as one contiguous
 // block with 16-byte stores (the records of a node are 6M float2, an even
 // count, and the block starts at a multiple of 256 records).
+__host__ __device__ constexpr int rec_f2(int M) { return 6 * M - 2; }
+
 __global__ __launch_bounds__(256) void k_pack_gather(const float2* __restrict__ real, float2* __restrict__ gf, int nr,
                                                      int nz, int M) {
-  extern __shared__ float4 rec4[];  // [256][6M] float2, 16-byte aligned
+  extern __shared__ float4 rec4[];  // [256][6M - 2] float2, 16-byte aligned
   float2* rec = reinterpret_cast<float2*>(rec4);
   const int64_t n = (int64_t)nr * nz;
   const int64_t node0 = (int64_t)blockIdx.x * 256;
   const int64_t node = node0 + threadIdx.x;
-  const int w = 6 * M;
-  if (node < n)
-    for (int m = 0; m < M; ++m)
+  const int w = rec_f2(M);
+  if (node < n) {
+    float2* r = rec + threadIdx.x * w;
+    r[0] = real[fidx(1, 0, M, nr, nz) + node];   // E-,0
+    r[1] = real[fidx(4, 0, M, nr, nz) + node];   // B-,0
+    r[2] = make_float2(real[fidx(2, 0, M, nr, nz) + node].x, real[fidx(5, 0, M, nr, nz) + node].x);
+    r[3] = make_float2(0.f, 0.f);
+    for (int m = 1; m < M; ++m)
 #pragma unroll
-      for (int c = 0; c < 6; ++c) rec[threadIdx.x * w + m * 6 + c] = real[fidx(c, m, M, nr, nz) + node];
+      for (int c = 0; c < 6; ++c) r[4 + 6 * (m - 1) + c] = real[fidx(c, m, M, nr, nz) + node];
+  }
   __syncthreads();
   const int64_t nodes = n - node0 < 256 ? n - node0 : 256;
   const int nq = (int)(nodes * w / 2);   // float4 count of the block
@@ -92,14 +103,24 @@ struct Gathered {
 template <int M>
 __device__ __forceinline__ void gather_node(Gathered<M>& acc, const float2* __restrict__ gf, int i, int j, int nz,
                                             float w_even, float w_odd) {
-  const float4* rec = reinterpret_cast<const float4*>(gf + ((size_t)i * nz + j) * 6 * M);
+  const float4* rec = reinterpret_cast<const float4*>(gf + ((size_t)i * nz + j) * rec_f2(M));
+  {
+    // mode 0: E-, B- (Hankel order -1: odd), real Ez, Bz (order 0: even)
+    const float4 a = rec[0], b = rec[1];
+    acc.f[0][1].x += w_odd * a.x;
+    acc.f[0][1].y += w_odd * a.y;
+    acc.f[0][4].x += w_odd * a.z;
+    acc.f[0][4].y += w_odd * a.w;
+    acc.f[0][2].x += w_even * b.x;
+    acc.f[0][5].x += w_even * b.y;
+  }
 #pragma unroll
-  for (int q = 0; q < 3 * M; ++q) {
-    const float4 v = rec[q];
+  for (int q = 0; q < 3 * (M - 1); ++q) {
+    const float4 v = rec[2 + q];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int e = 2 * q + h;
-      const int m = e / 6, c = e % 6;
+      const int m = 1 + e / 6, c = e % 6;
       // Hankel order: m+1 (E+, B+), m-1 (E-, B-), m (Ez, Bz)
       const bool odd = (c % 3 == 2) ? (m & 1) : ((m + 1) & 1);
       const float w = odd ? w_odd : w_even;
@@ -560,8 +581,8 @@ void launch_gather_push(const Parts& p, const float2* gf, const Grid& g, const S
   }
 }
 void launch_pack_gather(const float2* real, float2* gf, int nr, int nz, int M, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack_gather, dim3(nblk((int64_t)nr * nz, 256)), dim3(256), (size_t)256 * 6 * M * sizeof(float2),
-                     s, real, gf, nr, nz, M);
+  hipLaunchKernelGGL(k_pack_gather, dim3(nblk((int64_t)nr * nz, 256)), dim3(256),
+                     (size_t)256 * rec_f2(M) * sizeof(float2), s, real, gf, nr, nz, M);
 }
 void launch_keys(const Parts& p, const Grid& g, const DevState* st, uint32_t* key, int* count, int cap,
                  hipStream_t s) {
