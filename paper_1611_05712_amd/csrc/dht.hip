@@ -57,6 +57,24 @@ __device__ __forceinline__ void load_chunk(gcfloat_p __restrict__ at, gcfloat_p 
   }
 }
 
+// Output tile of this workgroup.  Workgroups are dealt round-robin to the
+// 8 XCDs (each with its own L2); when the column tiles come in multiples of 8,
+// the k-th workgroup of XCD x takes row tile k mod R of column tile
+// 8 (k div R) + x, so all R row tiles of one column block (which read the same
+// operand columns) run back to back on one XCD.  A bijection of the grid.
+__device__ __forceinline__ void gemm_tile_of(int& rt, int& ct) {
+  const int ncx = gridDim.x, nry = gridDim.y;
+  if ((ncx & 7) != 0) {
+    rt = blockIdx.y;
+    ct = blockIdx.x;
+    return;
+  }
+  const int lin = blockIdx.y * ncx + blockIdx.x;
+  const int k = lin >> 3;
+  rt = k % nry;
+  ct = (k / nry) * 8 + (lin & 7);
+}
+
 template <int BM, int BN>
 __device__ __forceinline__ void store_chunk(float* As, float* Bs, const float* ra, const float* rb) {
   using T = GemmTile<BM, BN>;
@@ -95,7 +113,9 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const float* const* __restrict
   gcfloat_p at = (gcfloat_p)AT[blockIdx.z];
   gcfloat_p x = (gcfloat_p)X[blockIdx.z];
   gfloat_p y = (gfloat_p)Y[blockIdx.z];
-  const int m0 = blockIdx.y * T::MT, n0 = blockIdx.x * T::NT;
+  int rt, ct;
+  gemm_tile_of(rt, ct);
+  const int m0 = rt * T::MT, n0 = ct * T::NT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   floatx16 acc[BM][BN];
 #pragma unroll
@@ -184,7 +204,9 @@ __global__ __launch_bounds__(256) void k_gemm_split(const float* const* __restri
   gcfloat_p at = (gcfloat_p)AT[blockIdx.z];
   gcfloat_p x = (gcfloat_p)X[blockIdx.z];
   gfloat_p y = (gfloat_p)Y[blockIdx.z];
-  const int m0 = blockIdx.y * T::MT, n0 = blockIdx.x * T::NT;
+  int rt, ct;
+  gemm_tile_of(rt, ct);
+  const int m0 = rt * T::MT, n0 = ct * T::NT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   floatx16 acc[BM][BN], acl[BM][BN];
 #pragma unroll

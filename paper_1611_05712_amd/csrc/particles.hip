@@ -450,9 +450,16 @@ __global__ __launch_bounds__(256) void k_scatter(Parts src, Parts dst, const uin
     r.sp = src.sp[i];
     rec[tid] = r;
   }
-  // bitonic sort of the 256 keys in registers: partners within a wavefront
-  // exchange through __shfl_xor, the three stages with stride >= 64 through LDS
-  for (int size = 2; size <= 256; size <<= 1) {
+  // The input is the previous step's sorted order pushed by at most a cell (a
+  // window move lowers every key alike), so many blocks arrive sorted: a block
+  // whose keys already ascend keeps (key, index) as it is.
+  sk[tid] = e;
+  __syncthreads();
+  const bool ascending = __syncthreads_and(tid == 255 || (uint32_t)(sk[tid] >> 32) <= (uint32_t)(sk[tid + 1] >> 32));
+  // otherwise a bitonic sort of the 256 keys in registers: partners within a
+  // wavefront exchange through __shfl_xor, the three stages with stride >= 64
+  // through LDS
+  for (int size = 2; size <= 256 && !ascending; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       uint64_t other;
       if (stride >= 64) {
