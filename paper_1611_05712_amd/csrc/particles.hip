@@ -413,12 +413,18 @@ __global__ __launch_bounds__(256) void k_scan_apply(int* __restrict__ count, int
 
 // --------------------------------------------------------------------------
 // scatter into cell order (removed particles dropped).  Block-level
-// multisplit: the 256 keys of a block are sorted (bitonic network on key then
-// original index, so the order is stable; in registers, with LDS only for the
-// stages whose partners sit in another wavefront), every distinct key reserves one
-// contiguous range of its cell with a single atomic, and thread t writes the
-// t-th particle of the sorted block, so particles bound for one cell leave
-// as one contiguous run even when the wake has scrambled the input order.
+// multisplit: every run of equal keys in a block reserves one contiguous range
+// of its cell with a single atomic, and thread t writes the t-th particle of
+// the block in key order, so particles bound for one cell leave as one
+// contiguous run even when the wake has scrambled the input order.
+//
+// The input is the previous step's sorted order pushed by at most a cell (a
+// window move lowers every key alike), so most blocks arrive with ascending
+// keys: such a block reserves its runs while its particle records are still in
+// flight and writes them from registers.  Any other block sorts its 256 keys
+// (bitonic network on key then original index, so the order is stable; in
+// registers, with LDS only for the stages whose partners sit in another
+// wavefront) and stages its records in LDS.
 // --------------------------------------------------------------------------
 struct PartRec {
   double x, y, z, uz;
@@ -426,46 +432,84 @@ struct PartRec {
   uint32_t sp;
 };
 
-__global__ __launch_bounds__(256) void k_scatter(Parts src, Parts dst, const uint32_t* __restrict__ key,
-                                                 int* __restrict__ cursor, const DevState* __restrict__ st,
-                                                 int ncells) {
-  __shared__ uint64_t sk[256];     // (key << 32) | local index
-  __shared__ PartRec rec[256];
-  __shared__ int base_of[256];     // destination of sorted slot t
-  const int tid = threadIdx.x;
-  const int i = blockIdx.x * 256 + tid;
-  const int n = st->n_part;
-  uint32_t k = (i < n) ? key[i] : kInvalidKey;
-  if (k >= (uint32_t)ncells) k = kInvalidKey;   // removed or past the end
-  uint64_t e = ((uint64_t)k << 32) | (uint32_t)tid;
-  if (k != kInvalidKey) {
-    PartRec r;
-    r.x = src.x[i];
-    r.y = src.y[i];
-    r.z = src.z[i];
-    r.ux = src.ux[i];
-    r.uy = src.uy[i];
-    r.uz = src.uz[i];
-    r.w = src.w[i];
-    r.sp = src.sp[i];
-    rec[tid] = r;
-  }
-  // The input is the previous step's sorted order pushed by at most a cell (a
-  // window move lowers every key alike), so many blocks arrive sorted: a block
-  // whose keys already ascend keeps (key, index) as it is.
-  sk[tid] = e;
+__device__ __forceinline__ uint32_t scatter_key(const uint32_t* __restrict__ key, int i, int n, int ncells) {
+  const uint32_t k = (i >= 0 && i < n) ? key[i] : kInvalidKey;
+  return k >= (uint32_t)ncells ? kInvalidKey : k;   // removed or past the end
+}
+
+// run head of every thread of the block from the per-thread "first of a run"
+// flags: the nearest head at or below tid.  wlast[w] is the last head of
+// wavefront w (-1 if none); thread 0 is always a head.
+__device__ __forceinline__ int run_head(bool first, int* wlast) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t heads = __ballot(first);
+  if (lane == 0) wlast[w] = heads ? (w << 6) + 63 - __clzll((long long)heads) : -1;
   __syncthreads();
-  const bool ascending = __syncthreads_and(tid == 255 || (uint32_t)(sk[tid] >> 32) <= (uint32_t)(sk[tid + 1] >> 32));
-  // otherwise a bitonic sort of the 256 keys in registers: partners within a
-  // wavefront exchange through __shfl_xor, the three stages with stride >= 64
-  // through LDS
-  for (int size = 2; size <= 256 && !ascending; size <<= 1) {
+  const uint64_t upto = heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1ull));
+  if (upto) return (w << 6) + 63 - __clzll((long long)upto);
+  int h = -1;
+  for (int v = 0; v < w; ++v) h = wlast[v] > h ? wlast[v] : h;
+  return h;
+}
+
+struct ScatterLds {
+  uint64_t sk[256];     // (key << 32) | local index
+  PartRec rec[256];
+  int base_of[256];     // destination of the run headed at t
+  int wlast[4];
+};
+
+__device__ __forceinline__ void write_rec(const Parts& dst, int d, double x, double y, double z, double uz, float ux,
+                                          float uy, float w, uint32_t sp) {
+  dst.x[d] = x;
+  dst.y[d] = y;
+  dst.z[d] = z;
+  dst.ux[d] = ux;
+  dst.uy[d] = uy;
+  dst.uz[d] = uz;
+  dst.w[d] = w;
+  dst.sp[d] = (uint8_t)sp;
+}
+
+// Thread tid of the block holds the record of key k (k_prev, k_next: the keys
+// of the neighbouring input positions; kInvalidKey drops a particle).  Every
+// thread of the block calls this.  The record travels as scalars: held in a
+// struct, the two write-outs below are merged over a pointer that is either
+// the registers' stack copy or LDS, and the copy lands in scratch memory.
+__device__ __forceinline__ void scatter_block(ScatterLds& L, uint32_t k, uint32_t k_prev, uint32_t k_next, double x,
+                                              double y, double z, double uz, float ux, float uy, float w, uint32_t sp,
+                                              const Parts& dst, int* __restrict__ cursor) {
+  const int tid = threadIdx.x;
+  const bool ascending = __syncthreads_and(tid == 255 || k <= k_next);
+  if (ascending) {
+    const int h = run_head(tid == 0 || k_prev != k, L.wlast);
+    const bool last = tid == 255 || k_next != k;
+    if (last && k != kInvalidKey) L.base_of[h] = atomicAdd(&cursor[k], tid - h + 1);
+    __syncthreads();
+    if (k != kInvalidKey) write_rec(dst, L.base_of[h] + (tid - h), x, y, z, uz, ux, uy, w, sp);
+    return;
+  }
+  if (k != kInvalidKey) {
+    PartRec& q = L.rec[tid];
+    q.x = x;
+    q.y = y;
+    q.z = z;
+    q.uz = uz;
+    q.ux = ux;
+    q.uy = uy;
+    q.w = w;
+    q.sp = sp;
+  }
+  uint64_t e = ((uint64_t)k << 32) | (uint32_t)tid;
+  // partners within a wavefront exchange through __shfl_xor, the three stages
+  // with stride >= 64 through LDS
+  for (int size = 2; size <= 256; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       uint64_t other;
       if (stride >= 64) {
-        sk[tid] = e;
+        L.sk[tid] = e;
         __syncthreads();
-        other = sk[tid ^ stride];
+        other = L.sk[tid ^ stride];
         __syncthreads();
       } else {
         const uint32_t lo = __shfl_xor((uint32_t)e, stride, 64);
@@ -476,37 +520,44 @@ __global__ __launch_bounds__(256) void k_scatter(Parts src, Parts dst, const uin
       e = keep_min ? (other < e ? other : e) : (other > e ? other : e);
     }
   }
-  sk[tid] = e;
+  L.sk[tid] = e;
   __syncthreads();
-  const uint64_t me = sk[tid];
-  const uint32_t mk = (uint32_t)(me >> 32);
-  const bool first = (tid == 0) || ((uint32_t)(sk[tid - 1] >> 32) != mk);
-  const bool last = (tid == 255) || ((uint32_t)(sk[tid + 1] >> 32) != mk);
-  // head of each run: inclusive prefix maximum of (first ? index : 0)
-  base_of[tid] = first ? tid : 0;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int v = tid >= off ? base_of[tid - off] : 0;
-    __syncthreads();
-    if (v > base_of[tid]) base_of[tid] = v;
-    __syncthreads();
-  }
-  const int h = base_of[tid];
-  __syncthreads();
-  if (last && mk != kInvalidKey) base_of[h] = atomicAdd(&cursor[mk], tid - h + 1);
+  const uint32_t mk = (uint32_t)(e >> 32);
+  const bool first = (tid == 0) || ((uint32_t)(L.sk[tid - 1] >> 32) != mk);
+  const bool last = (tid == 255) || ((uint32_t)(L.sk[tid + 1] >> 32) != mk);
+  const int h = run_head(first, L.wlast);
+  if (last && mk != kInvalidKey) L.base_of[h] = atomicAdd(&cursor[mk], tid - h + 1);
   __syncthreads();
   if (mk != kInvalidKey) {
-    const int d = base_of[h] + (tid - h);
-    const PartRec& r = rec[(uint32_t)me];
-    dst.x[d] = r.x;
-    dst.y[d] = r.y;
-    dst.z[d] = r.z;
-    dst.ux[d] = r.ux;
-    dst.uy[d] = r.uy;
-    dst.uz[d] = r.uz;
-    dst.w[d] = r.w;
-    dst.sp[d] = (uint8_t)r.sp;
+    const PartRec& q = L.rec[(uint32_t)e];
+    write_rec(dst, L.base_of[h] + (tid - h), q.x, q.y, q.z, q.uz, q.ux, q.uy, q.w, q.sp);
   }
+}
+
+// the copy into cell order of the pushed particles
+__global__ __launch_bounds__(256) void k_scatter(Parts src, Parts dst, const uint32_t* __restrict__ key,
+                                                 int* __restrict__ cursor, const DevState* __restrict__ st,
+                                                 int ncells) {
+  __shared__ ScatterLds L;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int n = st->n_part;
+  const uint32_t k = scatter_key(key, i, n, ncells);
+  const uint32_t k_prev = scatter_key(key, i - 1, n, ncells);
+  const uint32_t k_next = scatter_key(key, i + 1, n, ncells);
+  double x = 0.0, y = 0.0, z = 0.0, uz = 0.0;
+  float ux = 0.f, uy = 0.f, w = 0.f;
+  uint32_t sp = 0;
+  if (i < n) {   // requested before the reservation; a removed particle's record goes unused
+    x = src.x[i];
+    y = src.y[i];
+    z = src.z[i];
+    ux = src.ux[i];
+    uy = src.uy[i];
+    uz = src.uz[i];
+    w = src.w[i];
+    sp = src.sp[i];
+  }
+  scatter_block(L, k, k_prev, k_next, x, y, z, uz, ux, uy, w, sp, dst, cursor);
 }
 
 // --------------------------------------------------------------------------
