@@ -100,10 +100,18 @@ struct Gathered {
   float2 f[M][6];   // E+, E-, Ez, B+, B-, Bz per mode
 };
 
+// record (i, j) of the node-interleaved copy in HBM
 template <int M>
-__device__ __forceinline__ void gather_node(Gathered<M>& acc, const float2* __restrict__ gf, int i, int j, int nz,
-                                            float w_even, float w_odd) {
-  const float4* rec = reinterpret_cast<const float4*>(gf + ((size_t)i * nz + j) * rec_f2(M));
+struct GlobalRecs {
+  const float4* __restrict__ gf4;
+  int nz;
+  __device__ __forceinline__ const float4* operator()(int i, int j) const {
+    return gf4 + ((size_t)i * nz + j) * (rec_f2(M) / 2);
+  }
+};
+
+template <int M>
+__device__ __forceinline__ void gather_node(Gathered<M>& acc, const float4* rec, float w_even, float w_odd) {
   {
     // mode 0: E-, B- (Hankel order -1: odd), real Ez, Bz (order 0: even)
     const float4 a = rec[0], b = rec[1];
@@ -151,9 +159,9 @@ __device__ __forceinline__ void cartesian(const Gathered<M>& a, int cb, float2 e
   fz = zz;
 }
 
-template <int M>
-__device__ __forceinline__ void gather_eb(const float2* __restrict__ gf, const ShapePos& s, const Grid& g, float& Ex,
-                                          float& Ey, float& Ez, float& Bx, float& By, float& Bz) {
+template <int M, class Recs>
+__device__ __forceinline__ void gather_eb(const Recs& rec, const ShapePos& s, const Grid& g, float& Ex, float& Ey,
+                                          float& Ez, float& Bx, float& By, float& Bz) {
   Gathered<M> a;
 #pragma unroll
   for (int m = 0; m < M; ++m)
@@ -164,15 +172,15 @@ __device__ __forceinline__ void gather_eb(const float2* __restrict__ gf, const S
   const float wra = 1.f - s.fr, wrb = s.fr;
   const int ia = s.i0, ib = s.i0 + 1;
   if (ia == -1) {              // ghost across the axis: node 0 with (-1)^nu
-    gather_node<M>(a, gf, 0, ja, g.nz, wra * wza, -wra * wza);
-    gather_node<M>(a, gf, 0, jb, g.nz, wra * wzb, -wra * wzb);
+    gather_node<M>(a, rec(0, ja), wra * wza, -wra * wza);
+    gather_node<M>(a, rec(0, jb), wra * wzb, -wra * wzb);
   } else if (ia >= 0 && ia < g.nr) {
-    gather_node<M>(a, gf, ia, ja, g.nz, wra * wza, wra * wza);
-    gather_node<M>(a, gf, ia, jb, g.nz, wra * wzb, wra * wzb);
+    gather_node<M>(a, rec(ia, ja), wra * wza, wra * wza);
+    gather_node<M>(a, rec(ia, jb), wra * wzb, wra * wzb);
   }
   if (ib >= 0 && ib < g.nr) {
-    gather_node<M>(a, gf, ib, ja, g.nz, wrb * wza, wrb * wza);
-    gather_node<M>(a, gf, ib, jb, g.nz, wrb * wzb, wrb * wzb);
+    gather_node<M>(a, rec(ib, ja), wrb * wza, wrb * wza);
+    gather_node<M>(a, rec(ib, jb), wrb * wzb, wrb * wzb);
   }
   cartesian<M>(a, 0, s.eith, Ex, Ey, Ez);
   cartesian<M>(a, 3, s.eith, Bx, By, Bz);
@@ -209,7 +217,7 @@ __device__ __forceinline__ void gather_eb_cubic(const float2* __restrict__ gf, c
     for (int b = 0; b < 4; ++b) {
       const int j = (s.j0 - 1 + b) & (g.nz - 1);   // nz is a power of two
       const float w = wr[q] * wz[b];
-      gather_node<M>(a, gf, i, j, g.nz, w, ghost ? -w : w);
+      gather_node<M>(a, GlobalRecs<M>{reinterpret_cast<const float4*>(gf), g.nz}(i, j), w, ghost ? -w : w);
     }
   }
   cartesian<M>(a, 0, s.eith, Ex, Ey, Ez);
@@ -217,31 +225,21 @@ __device__ __forceinline__ void gather_eb_cubic(const float2* __restrict__ gf, c
 }
 
 // --------------------------------------------------------------------------
-// gather + Boris push + move + new cell key + key histogram.  Each thread
-// pushes kPushPer particles, blockDim apart, all their loads issued before any
-// of them is computed.  Measured at 2048 x 256: one particle per thread (83
-// instead of 95 VGPRs, twice the wavefronts of half the work) beats two, three
-// or four.
+// gather + Boris push + move + new cell key + key histogram, one particle per
+// thread.  Measured at 2048 x 256: one particle per thread beats two, three or
+// four with all their loads issued first (fewer VGPRs, more wavefronts).
 // --------------------------------------------------------------------------
-constexpr int kPushPer = 1;
-
 struct PushRec {
   double x, y, z, uz;
   float ux, uy;
   uint8_t sp;
 };
 
-template <int M, int SHAPE>
-__device__ __forceinline__ uint32_t push_one(PushRec& r, const float2* __restrict__ gf, const Grid& g,
-                                             const SpeciesConst& sc, double zmin, bool kill) {
-  if (kill && r.z < zmin) return (uint32_t)g.ncells;
-  const float qm = sc.qm[r.sp];
-  ShapePos s = shape_at(r.x, r.y, r.z, zmin, g);
-  float Ex, Ey, Ez, Bx, By, Bz;
-  if constexpr (SHAPE == 3) gather_eb_cubic<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
-  else gather_eb<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
-  // Boris rotation (J. P. Boris, 1970).  The transverse momenta and all
-  // increments are FP32; u_z accumulates its increments in FP64.
+// Boris rotation (J. P. Boris, 1970) and move; returns the new cell key.  The
+// transverse momenta and all increments are FP32; u_z accumulates its
+// increments in FP64.
+__device__ __forceinline__ uint32_t boris_move(PushRec& r, float qm, float Ex, float Ey, float Ez, float Bx, float By,
+                                               float Bz, const Grid& g, double zmin) {
   float eps = qm * (float)g.dt * 0.5f;
   float umx = r.ux + eps * Ex, umy = r.uy + eps * Ey;
   double umz = r.uz + (double)(eps * Ez);
@@ -266,58 +264,121 @@ __device__ __forceinline__ uint32_t push_one(PushRec& r, const float2* __restric
   return cell_key(shape_at(r.x, r.y, r.z, zmin, g), g);
 }
 
+// Field records a workgroup may stage in LDS.  Sorted by cell, the 256
+// particles of a workgroup usually sit in a few cells of one z column: their
+// nodes form a small box of records, which the workgroup copies into LDS with
+// coalesced loads once, and every particle then reads its four records from
+// LDS instead of through L1 (four records of 16-byte loads per particle were
+// the gather's main cost).  A workgroup whose box is larger (a column
+// boundary inside it, a scrambled or sparse region) reads from HBM as before.
+constexpr int kStageRecs = 128;
+
 template <int M, int SHAPE>
 __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __restrict__ gf, Grid g, SpeciesConst sc,
                                                      const DevState* __restrict__ st, uint32_t* __restrict__ key,
                                                      int* __restrict__ count) {
+  constexpr int R4 = rec_f2(M) / 2;   // float4 per record
+  __shared__ float4 stage[SHAPE == 1 ? kStageRecs * R4 : 1];
+  __shared__ int wbox[4][4];
   const int n = st->n_part;
   // XCD-aware order: the hardware deals workgroups round-robin over the 8
   // XCDs; each XCD gets one contiguous range of the active blocks, so the
   // field nodes shared by neighbouring particles stay in one L2
-  const int nact = (n + kPushPer * 256 - 1) / (kPushPer * 256);
+  const int nact = (n + 255) / 256;
   const int bx = blockIdx.x;
   if (bx >= nact) return;
   const int q8 = nact >> 3, r8 = nact & 7, x8 = bx & 7;
   const int lb = x8 * q8 + min(x8, r8) + (bx >> 3);
-  const int base = lb * (kPushPer * 256) + threadIdx.x;
+  const int tid = threadIdx.x;
+  const int i = lb * 256 + tid;
   const double zmin = st->zmin;
   const bool kill = g.moving_window && st->n_shift > 0;
-  PushRec r[kPushPer];
-#pragma unroll
-  for (int q = 0; q < kPushPer; ++q) {
-    const int i = base + q * 256;
-    if (i < n) {
-      r[q].x = p.x[i];
-      r[q].y = p.y[i];
-      r[q].z = p.z[i];
-      r[q].uz = p.uz[i];
-      r[q].ux = p.ux[i];
-      r[q].uy = p.uy[i];
-      r[q].sp = p.sp[i];
-    }
+  const GlobalRecs<M> grec{reinterpret_cast<const float4*>(gf), g.nz};
+  PushRec r;
+  bool live = false;
+  uint32_t k = kInvalidKey;
+  if (i < n) {
+    r.x = p.x[i];
+    r.y = p.y[i];
+    r.z = p.z[i];
+    r.uz = p.uz[i];
+    r.ux = p.ux[i];
+    r.uy = p.uy[i];
+    r.sp = p.sp[i];
+    live = !(kill && r.z < zmin);
+    if (!live) k = (uint32_t)g.ncells;
   }
-  uint32_t k[kPushPer];
-#pragma unroll
-  for (int q = 0; q < kPushPer; ++q) {
-    k[q] = kInvalidKey;
-    if (base + q * 256 < n) k[q] = push_one<M, SHAPE>(r[q], gf, g, sc, zmin, kill);
-  }
-#pragma unroll
-  for (int q = 0; q < kPushPer; ++q) {
-    const int i = base + q * 256;
-    if (i < n) {
-      if (k[q] != (uint32_t)g.ncells) {
-        p.x[i] = r[q].x;
-        p.y[i] = r[q].y;
-        p.z[i] = r[q].z;
-        p.uz[i] = r[q].uz;
-        p.ux[i] = r[q].ux;
-        p.uy[i] = r[q].uy;
+  ShapePos s;
+  if (live) s = shape_at(r.x, r.y, r.z, zmin, g);
+  float Ex = 0.f, Ey = 0.f, Ez = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
+  if constexpr (SHAPE == 3) {
+    if (live) gather_eb_cubic<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
+  } else {
+    // box of the records the workgroup reads: rows max(i0, 0) .. min(i0 + 1,
+    // nr - 1) (the ghost row -1 reads row 0), columns j0 .. j0 + 1
+    int ilo = INT_MAX, ihi = INT_MIN, jlo = INT_MAX, jhi = INT_MIN;
+    if (live) {
+      const int a = s.i0 < 0 ? 0 : s.i0;
+      const int b = s.i0 + 1 < g.nr ? s.i0 + 1 : g.nr - 1;
+      if (a <= b) {
+        ilo = a;
+        ihi = b;
+        jlo = s.j0;
+        jhi = s.j0 + 1;   // nz at the last column: its wrap to column 0 is not staged
       }
-      key[i] = k[q];
     }
-    wave_count(k[q], count);
+    for (int off = 32; off > 0; off >>= 1) {
+      ilo = min(ilo, __shfl_xor(ilo, off, 64));
+      ihi = max(ihi, __shfl_xor(ihi, off, 64));
+      jlo = min(jlo, __shfl_xor(jlo, off, 64));
+      jhi = max(jhi, __shfl_xor(jhi, off, 64));
+    }
+    const int wv = tid >> 6;
+    if ((tid & 63) == 0) {
+      wbox[wv][0] = ilo;
+      wbox[wv][1] = ihi;
+      wbox[wv][2] = jlo;
+      wbox[wv][3] = jhi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      ilo = min(ilo, wbox[v][0]);
+      ihi = max(ihi, wbox[v][1]);
+      jlo = min(jlo, wbox[v][2]);
+      jhi = max(jhi, wbox[v][3]);
+    }
+    const bool any = ilo <= ihi;   // some thread reads a record
+    const int ni = any ? ihi - ilo + 1 : 0, nj = any ? jhi - jlo + 1 : 0;
+    const bool staged = any && jhi < g.nz && ni * nj <= kStageRecs;   // uniform over the workgroup
+    if (staged) {
+      const int total = ni * nj * R4;
+      for (int q = tid; q < total; q += 256) {
+        const int rec = q / R4, part = q - rec * R4;
+        const int ii = rec / nj, jj = rec - ii * nj;
+        stage[q] = grec(ilo + ii, jlo + jj)[part];
+      }
+      __syncthreads();
+      const float4* st4 = stage;
+      const auto lrec = [=](int ii, int jj) { return st4 + ((ii - ilo) * nj + (jj - jlo)) * R4; };
+      if (live) gather_eb<M>(lrec, s, g, Ex, Ey, Ez, Bx, By, Bz);
+    } else if (live) {
+      gather_eb<M>(grec, s, g, Ex, Ey, Ez, Bx, By, Bz);
+    }
   }
+  if (live) k = boris_move(r, sc.qm[r.sp], Ex, Ey, Ez, Bx, By, Bz, g, zmin);
+  if (i < n) {
+    if (k != (uint32_t)g.ncells) {
+      p.x[i] = r.x;
+      p.y[i] = r.y;
+      p.z[i] = r.z;
+      p.uz[i] = r.uz;
+      p.ux[i] = r.ux;
+      p.uy[i] = r.uy;
+    }
+    key[i] = k;
+  }
+  wave_count(k, count);
 }
 
 // key + histogram of the current positions (no push): background deposit at setup
@@ -621,7 +682,7 @@ static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 void launch_gather_push(const Parts& p, const float2* gf, const Grid& g, const SpeciesConst& sc,
                         const DevState* st, uint32_t* key, int* count, int cap, hipStream_t s) {
-  dim3 grid(nblk(cap, kPushPer * 256));
+  dim3 grid(nblk(cap, 256));
   if (g.shape == 3) {
     switch (g.nmodes) {
       case 1: hipLaunchKernelGGL((k_gather_push<1, 3>), grid, dim3(256), 0, s, p, gf, g, sc, st, key, count); break;
