@@ -361,7 +361,9 @@ int pic_timing_read(pic_ctx* ctx, int timer, double* total_ms, int64_t* launches
 /* Launch parameters that change speed only (results agree to rounding). */
 typedef struct {
   int32_t gemm_tile_m;     /* output rows per Hankel-product workgroup tile: 32, 64 or 128
-                              (must divide nr) */
+                              (must divide nr), or 0 (the default): per product the
+                              largest tile whose workgroups fill the compute units in
+                              nearly whole rounds */
   int32_t deposit_chunk;   /* particles per deposit work item of a dense tile: 2048, 4096
                               or 8192 (tiles above 3x this are cut into such chunks) */
 } pic_tuning;
@@ -434,7 +436,9 @@ int pic_fft_z(void* data, int64_t rows, int nz, int inverse, void* hip_stream);
 /* Batched real matrix product Y_b = A_b X_b of `batch` pairs: A_b is n x n
  * float32 stored TRANSPOSED (at[k][m] = A[m][k]), X_b and Y_b are n x ncols
  * float32 row-major (a complex [n][nz] field is the real n x 2nz matrix).
- * a_t[b], x[b], y[b] are device arrays of `batch` device pointers.
+ * a_t[b], x[b], y[b] are device arrays of `batch` device pointers, each
+ * 16-byte aligned (operands are read as 16-byte vectors; any hipMalloc'd
+ * buffer at an offset of a multiple of 4 floats qualifies).
  * prec = pic_hankel_prec.  n is a multiple of 32, ncols a multiple of 128.
  * Errors: PIC_EINVAL. */
 int pic_dht_gemm(const void* const* a_t, const void* const* x, void* const* y, int batch,

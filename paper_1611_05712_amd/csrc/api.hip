@@ -505,7 +505,7 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species, i
   g.shape = cfg->shape_order == 3 ? 3 : 1;
   x->hz = halo_cells(cfg->dt, cfg->dz);
   x->hr = halo_cells(cfg->dt, cfg->dr);
-  x->gemm_bm = 2;
+  x->gemm_bm = 0;   // automatic per product
   hipStream_t s = x->stream;
   const int M = x->M, nr = x->nr, nz = x->nz;
   const size_t plane = plane_of(x);
@@ -1112,16 +1112,17 @@ int pic_free(pic_ctx* x) {
 // ---------------------------------------------------------------------------
 int pic_get_tuning(pic_ctx* x, pic_tuning* t) {
   if (!x || !t) return PIC_EINVAL;
-  t->gemm_tile_m = 32 * gemm_tile_bm(x->nr, x->gemm_bm);
+  t->gemm_tile_m = x->gemm_bm == 0 ? 0 : 32 * gemm_tile_bm(x->nr, x->gemm_bm);
   t->deposit_chunk = x->dep.chunk;
   return PIC_OK;
 }
 
 int pic_set_tuning(pic_ctx* x, const pic_tuning* t) {
   if (!x || !t) return PIC_EINVAL;
-  if (t->gemm_tile_m != 32 && t->gemm_tile_m != 64 && t->gemm_tile_m != 128) return PIC_EINVAL;
+  if (t->gemm_tile_m != 0 && t->gemm_tile_m != 32 && t->gemm_tile_m != 64 && t->gemm_tile_m != 128)
+    return PIC_EINVAL;
   if (t->deposit_chunk != 2048 && t->deposit_chunk != 4096 && t->deposit_chunk != 8192) return PIC_EINVAL;
-  if ((x->nr % t->gemm_tile_m) != 0) return PIC_EINVAL;
+  if (t->gemm_tile_m != 0 && (x->nr % t->gemm_tile_m) != 0) return PIC_EINVAL;
   x->gemm_bm = t->gemm_tile_m / 32;
   x->dep.chunk = t->deposit_chunk;
   x->dep.tile_max = 3 * t->deposit_chunk;
@@ -1433,11 +1434,11 @@ int pic_autotune(pic_ctx* x, int steps_per_trial, pic_tuning* best, double* best
     (void)hipEventDestroy(a);
     return PIC_EHIP;
   }
-  pic_tuning cand[9];
+  pic_tuning cand[12];
   int nc = 0;
-  for (int tm : {64, 128, 32})
+  for (int tm : {0, 64, 128, 32})
     for (int ch : {2048, 4096, 8192})
-      if (x->nr % tm == 0) cand[nc++] = pic_tuning{tm, ch};
+      if (tm == 0 || x->nr % tm == 0) cand[nc++] = pic_tuning{tm, ch};
   int rc = PIC_OK;
   double bms = 1e300;
   pic_tuning bt = cand[0];
@@ -1508,7 +1509,7 @@ int pic_dht_gemm(const void* const* a_t, const void* const* xin, void* const* y,
   if (!a_t || !xin || !y || batch < 0 || n < 32 || (n % 32) || ncols < 128 || (ncols % 128) || prec < 0 || prec > 2)
     return PIC_EINVAL;
   if (batch == 0) return PIC_OK;
-  launch_dht_gemm((const float* const*)a_t, (const float* const*)xin, (float* const*)y, batch, n, ncols, prec, 2,
+  launch_dht_gemm((const float* const*)a_t, (const float* const*)xin, (float* const*)y, batch, n, ncols, prec, 0,
                   (hipStream_t)hip_stream);
   return check_launch();
 }
