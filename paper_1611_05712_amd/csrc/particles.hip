@@ -395,53 +395,62 @@ __global__ __launch_bounds__(256) void k_keys(Parts p, Grid g, const DevState* _
 }
 
 // --------------------------------------------------------------------------
-// exclusive scan of the ncells + 1 bucket counts (3 passes)
+// exclusive scan of the ncells + 1 bucket counts (2 passes: block totals, then
+// every block adds the totals of the blocks before it itself, a few hundred
+// to two thousand values, instead of a one-workgroup pass over them in between)
 // --------------------------------------------------------------------------
 constexpr int kScanPerThread = 8;
 constexpr int kScanBlock = 256 * kScanPerThread;
 
+// wavefront scans (shuffles) and the four wavefront totals through LDS
 __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    int t = tid >= off ? sh[tid - off] : 0;
-    __syncthreads();
-    sh[tid] += t;
-    __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int inc = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += u;
   }
-  total = sh[255];
-  int ex = sh[tid] - v;
+  if (lane == 63) sh[w] = inc;
   __syncthreads();
-  return ex;
+  int pre = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) pre += i < w ? sh[i] : 0;
+  total = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return pre + inc - v;
+}
+
+typedef int intx4 __attribute__((ext_vector_type(4)));
+
+// a thread's kScanPerThread consecutive counts (zero past n); the arrays start
+// 256-byte aligned, so a full group is two aligned 16-byte loads
+__device__ __forceinline__ void load_counts(const int* __restrict__ c, int base, int n, int (&v)[kScanPerThread]) {
+  static_assert(kScanPerThread == 8, "two 16-byte vectors per thread");
+  if (base + 8 <= n) {
+    const intx4 a = *reinterpret_cast<const intx4*>(c + base);
+    const intx4 b = *reinterpret_cast<const intx4*>(c + base + 4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[e] = a[e];
+      v[e + 4] = b[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = base + e < n ? c[base + e] : 0;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_scan_blocks(const int* __restrict__ count, int n, int* __restrict__ bsum) {
-  __shared__ int sh[256];
+  __shared__ int sh[4];
   const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPerThread;
+  int v[kScanPerThread];
+  load_counts(count, base, n, v);
   int s = 0;
-  for (int e = 0; e < kScanPerThread; ++e)
-    if (base + e < n) s += count[base + e];
+#pragma unroll
+  for (int e = 0; e < kScanPerThread; ++e) s += v[e];
   int total;
   block_exclusive_scan(s, sh, total);
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(256) void k_scan_bsum(int* bsum, int nb) {
-  __shared__ int sh[256];
-  __shared__ int carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int b0 = 0; b0 < nb; b0 += 256) {
-    int i = b0 + threadIdx.x;
-    int v = i < nb ? bsum[i] : 0;
-    int total;
-    int ex = block_exclusive_scan(v, sh, total);
-    if (i < nb) bsum[i] = ex + carry;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += total;
-    __syncthreads();
-  }
 }
 
 // writes offset[0..n] (offset[n] = total), cursor = offset, count = 0;
@@ -449,26 +458,50 @@ __global__ __launch_bounds__(256) void k_scan_bsum(int* bsum, int nb) {
 __global__ __launch_bounds__(256) void k_scan_apply(int* __restrict__ count, int n, const int* __restrict__ bsum,
                                                     int* __restrict__ offset, int* __restrict__ cursor,
                                                     int ncells, DevState* st) {
-  __shared__ int sh[256];
+  __shared__ int sh[4];
+  __shared__ int wpart[4];
+  // this block's offset: the totals of the blocks before it
+  int pre = 0;
+  for (int i = threadIdx.x; i < (int)blockIdx.x; i += 256) pre += bsum[i];
+  for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off, 64);
+  if ((threadIdx.x & 63) == 0) wpart[threadIdx.x >> 6] = pre;
   const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPerThread;
   int v[kScanPerThread];
+  load_counts(count, base, n, v);
   int s = 0;
-  for (int e = 0; e < kScanPerThread; ++e) {
-    v[e] = (base + e < n) ? count[base + e] : 0;
-    s += v[e];
-  }
+#pragma unroll
+  for (int e = 0; e < kScanPerThread; ++e) s += v[e];
   int total;
-  int ex = block_exclusive_scan(s, sh, total) + bsum[blockIdx.x];
+  int ex = block_exclusive_scan(s, sh, total);   // its barriers also publish wpart
+  ex += wpart[0] + wpart[1] + wpart[2] + wpart[3];
+  int o[kScanPerThread];
+#pragma unroll
   for (int e = 0; e < kScanPerThread; ++e) {
-    int idx = base + e;
-    if (idx < n) {
-      offset[idx] = ex;
-      cursor[idx] = ex;
-      count[idx] = 0;
-      if (idx == ncells) st->n_live = ex;
-      if (idx == n - 1) offset[n] = ex + v[e];
-    }
+    o[e] = ex;
     ex += v[e];
+  }
+  if (base + 8 <= n) {
+    const intx4 a = {o[0], o[1], o[2], o[3]}, b = {o[4], o[5], o[6], o[7]}, z = {0, 0, 0, 0};
+    *reinterpret_cast<intx4*>(offset + base) = a;
+    *reinterpret_cast<intx4*>(offset + base + 4) = b;
+    *reinterpret_cast<intx4*>(cursor + base) = a;
+    *reinterpret_cast<intx4*>(cursor + base + 4) = b;
+    *reinterpret_cast<intx4*>(count + base) = z;
+    *reinterpret_cast<intx4*>(count + base + 4) = z;
+  } else {
+#pragma unroll
+    for (int e = 0; e < kScanPerThread; ++e)
+      if (base + e < n) {
+        offset[base + e] = o[e];
+        cursor[base + e] = o[e];
+        count[base + e] = 0;
+      }
+  }
+#pragma unroll
+  for (int e = 0; e < kScanPerThread; ++e) {
+    const int idx = base + e;
+    if (idx == ncells) st->n_live = o[e];
+    if (idx == n - 1) offset[n] = o[e] + v[e];
   }
 }
 
@@ -711,7 +744,6 @@ int scan_scratch_ints(int n) { return nblk(n, kScanBlock) + 1; }
 void launch_scan(int* count, int n, int* bsum, int* offset, int* cursor, int ncells, DevState* st, hipStream_t s) {
   int nb = nblk(n, kScanBlock);
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(256), 0, s, count, n, bsum);
-  hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(256), 0, s, bsum, nb);
   hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, count, n, bsum, offset, cursor, ncells, st);
 }
 void launch_scatter(const Parts& src, const Parts& dst, const uint32_t* key, int* cursor, const DevState* st,
