@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 MFMA_FP32_TFLOPS = 157.3       # MI355X dense FP32 matrix
 MFMA_BF16_TFLOPS = 2500.0      # dense bf16 / fp16
 
-# algorithmic traffic per unit of work (bytes), see the design doc
+# algorithmic traffic per unit of work (bytes)
 BYTES_PER_PARTICLE = {
     # particle record: x, y, z, u_z FP64 (32) + u_x, u_y, q*w FP32 (12) + species (1) = 45 B
     "gather_push": 91.0,   # read x,y,z,u (40) + species (1); write x,y,z,u (40) + key (4); field share ~6
@@ -244,8 +244,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the z-slab decomposition is described in DESIGN.md); run with --gpus 1",
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -9,7 +9,7 @@ that order by simulation means running the whole order scan.  Here a GELU
 MLP (5 -> 4 x 128 -> 2, trained on the GPU by the library's own forward,
 backward and Adam kernels) maps (2/p, k_p dz, k_p dr, gamma, witness charge)
 to the two errors; the order it picks is then checked by the plain
-simulation, which stays the judge: when the measured errors miss the
+simulation, which stays the referee: when the measured errors miss the
 threshold the next order up is run, so the answer is never worse than the
 scan's, only cheaper.
 """
@@ -131,9 +131,9 @@ class OrderSurrogate:
         self.net.close()
 
 
-def select_with_fallback(pick: int, judge: Callable[[int], Tuple[float, float]], threshold: float = THRESHOLD,
+def select_with_fallback(pick: int, referee: Callable[[int], Tuple[float, float]], threshold: float = THRESHOLD,
                          orders=ORDERS) -> Tuple[int, List[int]]:
-    """Starting at the picked order, ask the judge (the plain simulation of that
+    """Starting at the picked order, ask the referee (the plain simulation of that
     order against its infinite-order twin) and move one order up until both
     errors are below the threshold; infinite order is always acceptable.
     Returns the accepted order and the finite orders that were simulated."""
@@ -142,7 +142,7 @@ def select_with_fallback(pick: int, judge: Callable[[int], Tuple[float, float]],
         return 0, ran
     for p in [q for q in orders if q >= pick]:
         ran.append(p)
-        es, ee = judge(p)
+        es, ee = referee(p)
         if abs(es) < threshold and abs(ee) < threshold:
             return p, ran
     return 0, ran
@@ -167,7 +167,7 @@ def majority_order(scan: Dict[str, object], tuple_ids: Sequence[int], orders=ORD
 def compare_pickers(scan: Dict[str, object], held_ids: Sequence[int], pickers: Dict[str, Callable],
                     orders=ORDERS) -> Dict[str, Dict[str, int]]:
     """For each picker (set-up record -> order, 0 = infinite): over the held-out
-    set-ups, the simulations needed with the judge's fallback (settle_cost),
+    set-ups, the simulations needed with the referee's fallback (settle_cost),
     how often the accepted order is the scan's answer, and how often it is
     higher.  The scan itself needs every finite order plus the twin."""
     recs = {t["tuple"]: t for t in scan["tuples"]}
@@ -180,23 +180,23 @@ def compare_pickers(scan: Dict[str, object], held_ids: Sequence[int], pickers: D
         out["scan"]["runs"] += len(orders) + 1
         out["scan"]["exact"] += 1
         for name, pick_fn in pickers.items():
-            got, ran = select_with_fallback(pick_fn(t), table_judge(t), orders=orders)
+            got, ran = select_with_fallback(pick_fn(t), table_referee(t), orders=orders)
             out[name]["runs"] += settle_cost(ran)
             out[name]["exact"] += int(got == want)
             out[name]["over"] += int(rank[got] > rank[want])
     return out
 
 
-def table_judge(t: Dict[str, object]) -> Callable[[int], Tuple[float, float]]:
-    """Judge from a scan record (the errors its plain simulations measured)."""
-    def judge(p: int):
+def table_referee(t: Dict[str, object]) -> Callable[[int], Tuple[float, float]]:
+    """Referee from a scan record (the errors its plain simulations measured)."""
+    def referee(p: int):
         e = t["errors"][str(p)]
         return e["err_sigma_gamma"], e["err_eps"]
-    return judge
+    return referee
 
 
-class PlainJudge:
-    """Judge that runs the plain simulation: the infinite-order twin once, then
+class PlainReferee:
+    """Referee that runs the plain simulation: the infinite-order twin once, then
     each asked order, and measures Err_sigma_gamma and Err_eps of the witness."""
 
     def __init__(self, inst_by_order: Dict[int, object], steps: int, device="cuda:0"):

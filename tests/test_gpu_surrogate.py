@@ -62,7 +62,7 @@ def test_held_out_error_beats_the_data_mean(trained):
 
 def test_order_choice_beats_the_methods_without_the_network(trained):
     # per held-out set-up the order is settled by the plain simulation (the
-    # judge) starting from a pick and climbing one order at a time until the
+    # referee) starting from a pick and climbing one order at a time until the
     # errors pass; cost = the infinite-order twin (or, for a pick of infinity,
     # the production run itself) + every finite order simulated.  Against the
     # methods that use no network:
@@ -88,12 +88,12 @@ def test_order_choice_beats_the_methods_without_the_network(trained):
     assert net["exact"] > res["majority"]["exact"]
     assert net["runs"] < res["climb"]["runs"]
     assert net["runs"] <= 0.5 * res["scan"]["runs"]
-    # the judge keeps every accepted order within the threshold: never below the scan's answer
+    # the referee keeps every accepted order within the threshold: never below the scan's answer
     assert net["exact"] + net["over"] == n
 
 
-def test_plain_simulation_judges_a_held_out_pick(trained):
-    # the judge itself, live: the surrogate's order for one held-out set-up is
+def test_plain_simulation_referees_a_held_out_pick(trained):
+    # the referee itself, live: the surrogate's order for one held-out set-up is
     # run through the plain simulation against its infinite-order twin, and the
     # measured errors agree with the scan's record of the same runs
     from workloads import scan_instances
@@ -102,9 +102,9 @@ def test_plain_simulation_judges_a_held_out_pick(trained):
     insts = [i for i in scan_instances(n_tuples=len(scan["tuples"]), seed=scan["seed"], extra=0)
              if i.tuple_index == rec["tuple"]]
     pick = sur.choose_order(S.tuple_params(rec)) or S.ORDERS[-1]
-    judge = S.PlainJudge({i.order: i for i in insts}, scan["steps"])
-    es, ee = judge(pick)
+    referee = S.PlainReferee({i.order: i for i in insts}, scan["steps"])
+    es, ee = referee(pick)
     want = rec["errors"][str(pick)]
     assert es == pytest.approx(want["err_sigma_gamma"], rel=0.05, abs=2e-3)
     assert ee == pytest.approx(want["err_eps"], rel=0.05, abs=2e-3)
-    assert judge.runs == 2
+    assert referee.runs == 2

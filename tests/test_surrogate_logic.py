@@ -1,5 +1,5 @@
 """Host logic of the order surrogate: feature/target maps, the scan's
-required order, and the fallback that keeps the plain simulation the judge."""
+required order, and the fallback that keeps the plain simulation the referee."""
 import math
 
 import numpy as np
@@ -35,16 +35,16 @@ def test_required_order_is_the_lowest_passing_order():
 
 @pytest.mark.parametrize("pick,want,ran", [(8, 24, [8, 16, 24]), (24, 24, [24]), (32, 48, [32, 48]),
                                            (0, 0, [])])
-def test_fallback_climbs_until_the_judge_accepts(pick, want, ran):
+def test_fallback_climbs_until_the_referee_accepts(pick, want, ran):
     t = _record({8: (0.2, 0.01), 16: (0.04, 0.06), 24: (0.03, 0.02), 32: (0.06, 0.0),
                  48: (0.01, 0.0), 64: (0.0, 0.0)})
-    got, r = S.select_with_fallback(pick, S.table_judge(t))
+    got, r = S.select_with_fallback(pick, S.table_referee(t))
     assert got == want and r == ran
 
 
 def test_fallback_ends_at_infinite_order():
     t = _record({p: (0.5, 0.0) for p in S.ORDERS})
-    got, r = S.select_with_fallback(48, S.table_judge(t))
+    got, r = S.select_with_fallback(48, S.table_referee(t))
     assert got == 0 and r == [48, 64]
 
 
