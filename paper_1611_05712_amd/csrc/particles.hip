@@ -197,9 +197,9 @@ __device__ __forceinline__ void cubic_wts(float f, float (&w)[4]) {
   w[3] = f * f * f * (1.f / 6.f);
 }
 
-template <int M>
-__device__ __forceinline__ void gather_eb_cubic(const float2* __restrict__ gf, const ShapePos& s, const Grid& g,
-                                                float& Ex, float& Ey, float& Ez, float& Bx, float& By, float& Bz) {
+template <int M, class Recs>
+__device__ __forceinline__ void gather_eb_cubic(const Recs& rec, const ShapePos& s, const Grid& g, float& Ex,
+                                                float& Ey, float& Ez, float& Bx, float& By, float& Bz) {
   Gathered<M> a;
 #pragma unroll
   for (int m = 0; m < M; ++m)
@@ -217,7 +217,7 @@ __device__ __forceinline__ void gather_eb_cubic(const float2* __restrict__ gf, c
     for (int b = 0; b < 4; ++b) {
       const int j = (s.j0 - 1 + b) & (g.nz - 1);   // nz is a power of two
       const float w = wr[q] * wz[b];
-      gather_node<M>(a, GlobalRecs<M>{reinterpret_cast<const float4*>(gf), g.nz}(i, j), w, ghost ? -w : w);
+      gather_node<M>(a, rec(i, j), w, ghost ? -w : w);
     }
   }
   cartesian<M>(a, 0, s.eith, Ex, Ey, Ez);
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __re
                                                      const DevState* __restrict__ st, uint32_t* __restrict__ key,
                                                      int* __restrict__ count) {
   constexpr int R4 = rec_f2(M) / 2;   // float4 per record
-  __shared__ float4 stage[SHAPE == 1 ? kStageRecs * R4 : 1];
+  __shared__ float4 stage[kStageRecs * R4];
   __shared__ int wbox[4][4];
   const int n = st->n_part;
   // XCD-aware order: the hardware deals workgroups round-robin over the 8
@@ -311,20 +311,22 @@ __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __re
   ShapePos s;
   if (live) s = shape_at(r.x, r.y, r.z, zmin, g);
   float Ex = 0.f, Ey = 0.f, Ez = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
-  if constexpr (SHAPE == 3) {
-    if (live) gather_eb_cubic<M>(gf, s, g, Ex, Ey, Ez, Bx, By, Bz);
-  } else {
-    // box of the records the workgroup reads: rows max(i0, 0) .. min(i0 + 1,
-    // nr - 1) (the ghost row -1 reads row 0), columns j0 .. j0 + 1
+  {
+    // box of the records the workgroup reads, over its particles: linear
+    // shapes rows max(i0, 0) .. min(i0 + 1, nr - 1) (the ghost row -1 reads
+    // row 0), columns j0 .. j0 + 1; cubic shapes rows max(i0 - 1, 0) ..
+    // min(i0 + 2, nr - 1) (ghost rows -1, -2 read rows 0, 1), columns
+    // j0 - 1 .. j0 + 2.  A box that wraps around z is not staged.
+    constexpr int kLo = SHAPE == 3 ? 1 : 0, kHi = SHAPE == 3 ? 2 : 1;
     int ilo = INT_MAX, ihi = INT_MIN, jlo = INT_MAX, jhi = INT_MIN;
     if (live) {
-      const int a = s.i0 < 0 ? 0 : s.i0;
-      const int b = s.i0 + 1 < g.nr ? s.i0 + 1 : g.nr - 1;
+      const int a = s.i0 - kLo < 0 ? 0 : s.i0 - kLo;
+      const int b = s.i0 + kHi < g.nr ? s.i0 + kHi : g.nr - 1;
       if (a <= b) {
         ilo = a;
         ihi = b;
-        jlo = s.j0;
-        jhi = s.j0 + 1;   // nz at the last column: its wrap to column 0 is not staged
+        jlo = s.j0 - kLo;
+        jhi = s.j0 + kHi;
       }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __re
     }
     const bool any = ilo <= ihi;   // some thread reads a record
     const int ni = any ? ihi - ilo + 1 : 0, nj = any ? jhi - jlo + 1 : 0;
-    const bool staged = any && jhi < g.nz && ni * nj <= kStageRecs;   // uniform over the workgroup
+    const bool staged = any && jlo >= 0 && jhi < g.nz && ni * nj <= kStageRecs;   // uniform over the workgroup
     if (staged) {
       const int total = ni * nj * R4;
       for (int q = tid; q < total; q += 256) {
@@ -361,9 +363,13 @@ __global__ __launch_bounds__(256) void k_gather_push(Parts p, const float2* __re
       __syncthreads();
       const float4* st4 = stage;
       const auto lrec = [=](int ii, int jj) { return st4 + ((ii - ilo) * nj + (jj - jlo)) * R4; };
-      if (live) gather_eb<M>(lrec, s, g, Ex, Ey, Ez, Bx, By, Bz);
+      if (live) {
+        if constexpr (SHAPE == 3) gather_eb_cubic<M>(lrec, s, g, Ex, Ey, Ez, Bx, By, Bz);
+        else gather_eb<M>(lrec, s, g, Ex, Ey, Ez, Bx, By, Bz);
+      }
     } else if (live) {
-      gather_eb<M>(grec, s, g, Ex, Ey, Ez, Bx, By, Bz);
+      if constexpr (SHAPE == 3) gather_eb_cubic<M>(grec, s, g, Ex, Ey, Ez, Bx, By, Bz);
+      else gather_eb<M>(grec, s, g, Ex, Ey, Ez, Bx, By, Bz);
     }
   }
   if (live) k = boris_move(r, sc.qm[r.sp], Ex, Ey, Ez, Bx, By, Bz, g, zmin);
