@@ -830,16 +830,21 @@ __global__ __launch_bounds__(256) void k_deposit_combine(const int* __restrict__
       }
     }
   }
-  // every load in flight at once: unused slots repeat the first tile with weight 0
+  // every load in flight at once; a slot no lane of the wavefront needs (the
+  // second r tile away from tile edges) is skipped by the whole wavefront
   int cs[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) cs[q] = chunk_start[tq[q < nt ? q : 0]];
   float x[4][NV];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const float* qp = scratch + (size_t)cs[q] * nacc + toff[q < nt ? q : 0];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) x[q][v] = qp[v * B::NODES];
+    for (int v = 0; v < NV; ++v) x[q][v] = 0.f;
+    if (q < nt) {
+      const float* qp = scratch + (size_t)cs[q] * nacc + toff[q];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[q][v] = qp[v * B::NODES];
+    }
   }
   float acc[NV];
 #pragma unroll
