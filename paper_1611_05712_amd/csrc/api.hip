@@ -1136,6 +1136,9 @@ namespace {
 // capture are restored: nothing ran.
 int capture_graph(pic_ctx* x) {
   if (x->graph_ok) {
+    // the previous graph's replays may still run on the stream: wait for
+    // them before its executable (and the memory its launches use) is freed
+    if (hipStreamSynchronize(x->stream) != hipSuccess) return PIC_EHIP;
     (void)hipGraphExecDestroy(x->graph);
     x->graph_ok = false;
   }
@@ -1274,6 +1277,9 @@ int batch_parity(const pic_batch* b) {
 
 int batch_capture(pic_batch* b) {
   if (b->exec) {
+    // wait for the previous graph's replays on the lead stream before its
+    // executable is freed
+    if (hipStreamSynchronize(b->lead) != hipSuccess) return PIC_EHIP;
     (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
   }

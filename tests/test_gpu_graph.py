@@ -103,7 +103,6 @@ def test_set_tuning_rejects_unsupported_values():
             sim.set_tuning(tm, ch)
 
 
-@pytest.mark.skip(reason="the batched-graph path has ended this test's process with a host segmentation fault (inside pic_batch_step, and in eager steps of other contexts after a batch was freed); the cause is not found, so the path is not run here until it is")
 def test_batch_matches_individual_runs():
     from paper_1611_05712_amd import batch_step
     wls = [preset("small"), preset("tiny"), preset("small", seed=3)]
@@ -120,7 +119,6 @@ def test_batch_matches_individual_runs():
         _moments_close(bs, ss, name)
 
 
-@pytest.mark.skip(reason="the batched-graph path has ended this test's process with a host segmentation fault (inside pic_batch_step, and in eager steps of other contexts after a batch was freed); the cause is not found, so the path is not run here until it is")
 def test_batch_graph_over_several_runs_and_a_tuning_change():
     """One graph for three instances (two grids, a finite and the infinite
     order): runs of 4, then 3 (an odd step runs eagerly), a tuning change of
