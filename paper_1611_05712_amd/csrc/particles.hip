@@ -267,10 +267,11 @@ __device__ __forceinline__ uint32_t boris_move(PushRec& r, float qm, float Ex, f
 // Field records a workgroup may stage in LDS.  Sorted by cell, the 256
 // particles of a workgroup usually sit in a few cells of one z column: their
 // nodes form a small box of records, which the workgroup copies into LDS with
-// coalesced loads once, and every particle then reads its four records from
-// LDS instead of through L1 (four records of 16-byte loads per particle were
-// the gather's main cost).  A workgroup whose box is larger (a column
-// boundary inside it, a scrambled or sparse region) reads from HBM as before.
+// coalesced loads once, and every particle then reads its records from LDS
+// instead of through L1 (the records, read with 16-byte loads by every
+// particle, dominate the gather's cost).  A workgroup whose box is larger (a
+// column boundary inside it, a scrambled or sparse region) reads the records
+// from the HBM copy.
 constexpr int kStageRecs = 128;
 
 template <int M, int SHAPE>
@@ -401,9 +402,9 @@ __global__ __launch_bounds__(256) void k_keys(Parts p, Grid g, const DevState* _
 }
 
 // --------------------------------------------------------------------------
-// exclusive scan of the ncells + 1 bucket counts (2 passes: block totals, then
-// every block adds the totals of the blocks before it itself, a few hundred
-// to two thousand values, instead of a one-workgroup pass over them in between)
+// exclusive scan of the ncells + 1 bucket counts in 2 passes: block totals,
+// then every block adds up the totals of the blocks before it (a few hundred
+// to two thousand values) and scans its own counts
 // --------------------------------------------------------------------------
 constexpr int kScanPerThread = 8;
 constexpr int kScanBlock = 256 * kScanPerThread;
