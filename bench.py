@@ -253,10 +253,16 @@ def main():
         n = args.copy_calibration // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
-        for _ in range(5):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev[0].record()
+        for k in range(5):
             b.copy_(a)
+            ev[k + 1].record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": 4 * n, "launches": 5}))
+        # copies 2-5 (the first one warms up): read + write bytes per time
+        ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(1, 5)]
+        print(json.dumps({"copy_bytes": 4 * n, "launches": 5, "ms_per_copy": round(sum(ms) / 4, 4),
+                          "read_plus_write_TB_s": round(2 * 4 * n / (sum(ms) / 4) / 1e9, 3)}))
         return
     if args.scan:
         scan_bench(args)
