@@ -30,6 +30,8 @@
 // the LDS block of the tile's first work item before the FP32 rounding, so
 // the rounding acts on the net charge, not on two order-one densities that
 // nearly cancel.
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
@@ -284,6 +286,71 @@ __device__ __forceinline__ void cubic_deposit(double* __restrict__ lds, const fl
   }
 }
 
+// Cubic shapes: the particles of one run share the cell of x^{n+1}, hence the
+// 4 x 4 nodes of their rho^{n+1} stencil; a lane sums the 16 node weights
+// times the K values in registers and adds them to the block once per run
+// (cubic_deposit's node mapping, the ghost sign applied at the flush).
+template <int K>
+struct CubAcc {
+  uint32_t key;
+  float a[16 * K];
+};
+
+struct NoCubAcc {   // linear shapes: no cubic accumulator
+  uint32_t key = kInvalidKey;
+};
+
+template <int K>
+__device__ __forceinline__ void cub_reset(CubAcc<K>& A, uint32_t key) {
+  A.key = key;
+#pragma unroll
+  for (int i = 0; i < 16 * K; ++i) A.a[i] = 0.f;
+}
+
+template <int K>
+__device__ __forceinline__ void cub_add(CubAcc<K>& A, const float (&v)[K], float fz, float fr) {
+  float wz[4], wr[4];
+  cubic_weights(fz, wz);
+  cubic_weights(fr, wr);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const float w = wr[a] * wz[b];
+#pragma unroll
+      for (int k = 0; k < K; ++k) A.a[(4 * a + b) * K + k] = fmaf(w, v[k], A.a[(4 * a + b) * K + k]);
+    }
+}
+
+template <int TR, int H, int K, class Set, class OffFn>
+__device__ __forceinline__ void cub_flush(double* __restrict__ lds, const CubAcc<K>& A, const Grid& g, int J0,
+                                          int C0, OffFn off) {
+  using B = Blk<TR, H>;
+  const int j0 = (int)(A.key >> 11), i0 = (int)(A.key & 2047u) - 1;
+  int bz0 = j0 - 1 - (J0 - H);
+  if (bz0 < 0) bz0 += g.nz;
+  if (bz0 >= g.nz) bz0 -= g.nz;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int i = i0 - 1 + a;
+    const bool ghost = i < 0;
+    if (ghost) i = -1 - i;
+    const int br = i - (C0 - 1 - H);
+    if (i >= g.nr || br < 0 || br >= B::BR) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int bz = bz0 + b;
+      if (bz < 0 || bz >= B::BZ) continue;
+      const int node = br * B::BZ + bz;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float x = A.a[(4 * a + b) * K + k];
+        atomicAdd(lds + off(k) + node, (double)(ghost && Set::parity(k) ? -x : x));
+      }
+    }
+  }
+}
+
 // Register accumulator of one position kind: the cell key it belongs to and
 // the K values times the four node weights (ia,j0), (ia,j0+1), (ib,j0),
 // (ib,j0+1).  A run adds at most a few particles before it is flushed into
@@ -514,6 +581,8 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
   }
   Acc<RS::K> An, A1;
   Acc2<JS::K> AJ;
+  std::conditional_t<SHAPE == 3, CubAcc<RS::K>, NoCubAcc> Cb;   // cubic shapes: rho^{n+1} of the run
+  if constexpr (SHAPE == 3) cub_reset(Cb, kInvalidKey);
   acc_reset(An, kInvalidKey);
   acc_reset(A1, kInvalidKey);
   acc_reset(AJ.a, kInvalidKey);
@@ -578,7 +647,7 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
     for (int r0 = 0; r0 < nruns; r0 += 256) {
       const int r = r0 + tid;
       int len = 0, idx0 = 0;
-      uint32_t rkey = A1.key;
+      uint32_t rkey = SHAPE == 3 ? Cb.key : A1.key;
       if (r < nruns) {
         int lo = 0, hi = kCells;   // runpref[lo] <= r < runpref[hi]
         while (hi - lo > 1) {
@@ -594,7 +663,13 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
         idx0 = rowstart[row] + (start - rowpref[row]);
         rkey = (uint32_t)(J0 + row) * 2048u + (uint32_t)(C0 + col);
       }
-      if (kRho1J && rkey != A1.key) {
+      if constexpr (SHAPE == 3) {
+        if (kRho1J && rkey != Cb.key) {
+          if (Cb.key != kInvalidKey)
+            cub_flush<TR, H, RS::K, RS>(lds, Cb, g, J0, C0, [](int k) { return RS::off(4, k); });
+          cub_reset(Cb, rkey);
+        }
+      } else if (kRho1J && rkey != A1.key) {
         if (A1.key != kInvalidKey)
           acc_flush<TR, H, RS::K, RS>(lds, A1, g, J0, C0, [](int k) { return RS::off(4, k); });
         acc_reset(A1, rkey);
@@ -628,7 +703,10 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
               const ShapePos s = shape_at(x, y, z, zmin, g);
               float v[RS::K];
               RS::values(qw, s.eith, v);
-              cubic_deposit<TR, H, RS::K, RS>(lds, v, s, g, J0, C0, [](int k) { return RS::off(4, k); });
+              // the run's cell fixes the stencil, except in the last key
+              // column, which also holds particles beyond the last node
+              if ((Cb.key & 2047u) < (uint32_t)g.nr) cub_add(Cb, v, s.fz, s.fr);
+              else cubic_deposit<TR, H, RS::K, RS>(lds, v, s, g, J0, C0, [](int k) { return RS::off(4, k); });
               const ShapePos sh = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy,
                                            z - 0.5 * dt * (double)vz, zmin, g);
               float vj[JS::K];
@@ -682,6 +760,9 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
     }
   }   // pieces
   if (kRho1J) {
+    if constexpr (SHAPE == 3) {
+      if (Cb.key != kInvalidKey) cub_flush<TR, H, RS::K, RS>(lds, Cb, g, J0, C0, [](int k) { return RS::off(4, k); });
+    }
     if (A1.key != kInvalidKey) acc_flush<TR, H, RS::K, RS>(lds, A1, g, J0, C0, [](int k) { return RS::off(4, k); });
     if (AJ.a.key != kInvalidKey) acc_flush<TR, H, JS::K, JS>(lds, AJ.a, g, J0, C0, [](int k) { return JS::off(k); });
     if (AJ.b.key != kInvalidKey) acc_flush<TR, H, JS::K, JS>(lds, AJ.b, g, J0, C0, [](int k) { return JS::off(k); });
