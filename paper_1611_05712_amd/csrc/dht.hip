@@ -335,13 +335,16 @@ static int device_cus() {
 // the last round busy), else the one that wastes the least of its last round.
 // At nr = 256, 2 nz = 4096: the 10 forward products take 64 rows (1280
 // workgroups, 5 per unit; 128 rows would leave half of the third round idle),
-// the 12 inverse ones 128 rows (768, 3 per unit).
-int gemm_pick_bm(int n, int ncols, int batch, int pref_bm) {
+// the 12 inverse ones 128 rows (768, 3 per unit).  The split products stop at
+// 64 rows: their 128-row tile holds hi and lo accumulators in 256 registers
+// per lane, one wavefront per SIMD.
+int gemm_pick_bm(int n, int ncols, int batch, int pref_bm, int prec) {
   if (pref_bm > 0) return gemm_tile_bm(n, pref_bm);
   const double cus = device_cus();
   int best = 1;
   double best_eff = -1.0;
   for (int bm : {4, 2, 1}) {
+    if (prec != 0 && bm > 2) continue;
     if (n % (32 * bm)) continue;
     const double rounds = (double)(ncols / 128) * (n / (32 * bm)) * batch / cus;
     const double eff = rounds / std::ceil(rounds);
@@ -356,7 +359,7 @@ int gemm_pick_bm(int n, int ncols, int batch, int pref_bm) {
 
 void launch_dht_gemm(const float* const* at, const float* const* x, float* const* y, int batch, int n, int ncols,
                      int prec, int pref_bm, hipStream_t s, int* nonfinite) {
-  const int bm = gemm_pick_bm(n, ncols, batch, pref_bm);
+  const int bm = gemm_pick_bm(n, ncols, batch, pref_bm, prec);
   if (bm == 4) launch_tile<4, 1>(at, x, y, batch, n, ncols, prec, nonfinite, s);
   else if (bm == 2) launch_tile<2, 1>(at, x, y, batch, n, ncols, prec, nonfinite, s);
   else launch_tile<1, 1>(at, x, y, batch, n, ncols, prec, nonfinite, s);
