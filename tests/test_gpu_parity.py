@@ -387,6 +387,29 @@ def test_full_cycle_one_step_fields(name):
             assert _rel(sim.get_field(m, cn), want) < FIELD_TOL, (m, cn)
 
 
+def test_full_cycle_longest_z_one_step_fields():
+    """One full cycle at the longest z supported (4096 cells, where the z-FFT
+    takes 16 values per thread) with 128 radial cells (the inverse Hankel
+    products take 128-row tiles, the forward ones 64), p = 32, moving window,
+    a sparse plasma and a drive bunch: every field component of both modes
+    against the oracle's step."""
+    from workloads import _bunch_species, _plasma_species
+    nz, nr, dz, dr = 4096, 128, 0.02, 0.05
+    ele, ion = _plasma_species(nz, nr, dz, dr, 0.0, ppc=(1, 1, 1))
+    drive = _bunch_species("drive", 20000, 100e-12, 1000.0, 0.3, 0.4, 0.7 * nz * dz, 11, True)
+    wl = Workload("long-z", nz, nr, 2, 32, dz, dr, dz, 0.0, True, KPERP_JM_ZEROS, 1, [ele, ion, drive])
+    sim = _sim(wl)
+    o = OracleSim(wl)
+    sim.step(1)
+    o.step(1)
+    for m in range(2):
+        for c, cn in enumerate(COMPS):
+            want = (o.E if c < 3 else o.B)[m, c % 3]
+            if np.abs(want).max() < 1e-12:
+                continue
+            assert _rel(sim.get_field(m, cn), want) < FIELD_TOL, (m, cn, _rel(sim.get_field(m, cn), want))
+
+
 def test_full_cycle_small_ten_steps_beam_moments():
     wl = preset("small")
     sim = _sim(wl)
