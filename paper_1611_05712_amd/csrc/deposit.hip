@@ -803,6 +803,381 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
   for (int e = tid; e < nacc; e += blockDim.x) dst[e] = (float)lds[e];
 }
 
+// ---------------------------------------------------------------------------
+// Steady-state deposit (J^{n+1/2} and rho^{n+1}; rho^n carried over), linear
+// shapes: kLPR lanes per run of at most kRun particles of one cell, lane q
+// taking particles q, q + kLPR, ... of it.  The runs of a round are
+// consecutive in memory, so a wavefront's loads stay within a few lines.  A
+// lane sums its particles' node contributions in registers, the group then
+// sums over its lanes by a reduce-scatter (exchange steps inside the group,
+// each halving what a lane keeps), after which lane q holds the sums of the
+// q-th block of entries and issues their FP64 LDS atomics.
+//   * rho^{n+1}: every particle of a run is in the run's cell;
+//   * J^{n+1/2}: particles whose half-step cell is the run's cell join its
+//     sums; of the others, those in the cell of the group's first such
+//     particle are summed into a second set; any further cell deposits
+//     particle by particle.
+// ---------------------------------------------------------------------------
+constexpr int kLPR = 4;              // lanes per run
+constexpr int kPPL = kRun / kLPR;    // particles per lane and run
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+// one exchange step over the first N entries: a lane keeps the upper half when
+// `up`, else the lower one, and adds the partner's copy of the half it keeps
+// (the partner keeps the other half)
+template <int N, int CTRL, int CAP>
+__device__ __forceinline__ void rs_step(float (&a)[CAP], bool up) {
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const float lo = a[i], hi = a[N / 2 + i];
+    const float send = up ? lo : hi;
+    const float keep = up ? hi : lo;
+    a[i] = keep + dpp_mov<CTRL>(send);
+  }
+}
+
+// sum over the kLPR lanes of a group; afterwards lane q holds the sums of
+// entries q*N/kLPR .. (q+1)*N/kLPR - 1 in a[0 .. N/kLPR)
+template <int N>
+__device__ __forceinline__ void reduce_scatter(float (&a)[N], int q) {
+  static_assert(N % kLPR == 0, "entries per group lane");
+  if constexpr (kLPR == 8) {
+    rs_step<N, 0x141>(a, (q & 4) != 0);   // partner q ^ 7 (mirror within eight lanes)
+    rs_step<N / 2, 0x4E>(a, (q & 2) != 0);   // partner q ^ 2
+    rs_step<N / 4, 0xB1>(a, (q & 1) != 0);   // partner q ^ 1
+  } else {
+    static_assert(kLPR == 4, "four or eight lanes per run");
+    rs_step<N, 0x4E>(a, (q & 2) != 0);
+    rs_step<N / 2, 0xB1>(a, (q & 1) != 0);
+  }
+}
+
+__host__ __device__ constexpr int pad_lpr(int n) { return (n + kLPR - 1) / kLPR * kLPR; }
+
+// FP64 LDS atomics of lane q's block of entries of a reduced set.  Entry
+// e = 4 k + n is value k (rho^{n+1} values first when kRho) at node n of the
+// cell `key`: n = 0, 1 the inner radial node at j0, j0 + 1; n = 2, 3 the
+// outer one.
+template <int TR, int H, int M, int N, bool kRho>
+__device__ __forceinline__ void flush_block(double* __restrict__ lds, const float (&a)[N], uint32_t key,
+                                           const Grid& g, int J0, int C0, int q) {
+  using B = Blk<TR, H>;
+  using RS = RhoSet<M, B::NODES>;
+  using JS = JSet<M, B::NODES>;
+  constexpr int NR = kRho ? 4 * RS::K : 0;
+  constexpr int NE = NR + 4 * JS::K;
+  ShapePos s;
+  s.j0 = (int)(key >> 11);
+  s.i0 = (int)(key & 2047u) - 1;
+  const Local<TR, H> L = localize<TR, H>(s, g, J0, C0);
+#pragma unroll
+  for (int i = 0; i < N / kLPR; ++i) {
+    const int e = q * (N / kLPR) + i;
+    if (e >= NE) continue;
+    int off, par;
+    if (kRho && e < NR) {
+      off = RS::off(4, e >> 2);
+      par = RS::parity(e >> 2);
+    } else {
+      off = JS::off((e - NR) >> 2);
+      par = JS::parity((e - NR) >> 2);
+    }
+    const int n = e & 3;
+    if (n < 2) {
+      if (L.sa_even != 0.f) atomicAdd(lds + L.na + off + n, (double)(par ? L.sa_odd * a[i] : a[i]));
+    } else if (L.sb != 0.f) {
+      atomicAdd(lds + L.nb + off + (n - 2), (double)a[i]);
+    }
+  }
+}
+
+// one particle's shape data for the lane-group deposit
+template <int M>
+struct LanePart {
+  ShapePos s, sh;          // x^{n+1}, x^{n+1/2}
+  uint32_t kh;             // cell key of x^{n+1/2}
+  float vr[1 + 2 * (M - 1)];
+  float vj[3 + 6 * (M - 1)];
+};
+
+template <int TR, int H, int M>
+__global__ __launch_bounds__(256) void k_deposit_lanes(Parts p, const int* __restrict__ offset,
+                                                       const int* __restrict__ nchunk,
+                                                       const int* __restrict__ chunk_start,
+                                                       float* __restrict__ scratch, const double* __restrict__ ionblk,
+                                                       Grid g, TileGeom tg, DevState* st) {
+  using B = Blk<TR, H>;
+  using RS = RhoSet<M, B::NODES>;
+  using JS = JSet<M, B::NODES>;
+  extern __shared__ double lds[];
+  constexpr int nacc = Vals<M>::N * B::NODES;
+  constexpr int kCells = kTZ * TR;
+  constexpr int kGroups = 256 / kLPR;          // runs per round
+  constexpr int EA = pad_lpr(4 * (RS::K + JS::K));
+  constexpr int EB = pad_lpr(4 * JS::K);
+  constexpr uint32_t kGroupMask = (1u << kLPR) - 1u;
+  __shared__ int rowstart[kTZ];
+  __shared__ int rowpref[kTZ + 1];
+  __shared__ uint16_t runpref[kCells + 1];
+  __shared__ int cfirst[kCells];   // sorted index of each cell's first particle (clipped to the work item)
+  __shared__ int ccount[kCells];   // its particles in the work item
+  __shared__ int wsum[4];
+  __shared__ int s_tile;
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (b == 0 && tid == 0) {
+    st->n_part = st->n_live;
+    if (chunk_start[tg.ntiles] > (int)gridDim.x) st->overflow = 2;   // work list larger than the launch
+  }
+  if (b >= chunk_start[tg.ntiles]) return;   // uniform per workgroup
+  if (tid == 0) {
+    int lo = 0, hi = tg.ntiles;   // chunk_start[lo] <= b < chunk_start[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (chunk_start[mid] <= b) lo = mid;
+      else hi = mid;
+    }
+    s_tile = lo;
+  }
+  for (int e = tid; e < nacc; e += blockDim.x) lds[e] = 0.0;
+  __syncthreads();
+  const int t = s_tile;
+  const int chunk = b - chunk_start[t];
+  const int J0 = (t % tg.ntz) * kTZ, C0 = (t / tg.ntz) * TR;
+  const int C1 = min(C0 + TR, g.ncol);
+  if (tid < kTZ) {
+    const int j = J0 + tid;
+    const int a = offset[j * g.ncol + C0];
+    rowstart[tid] = a;
+    rowpref[tid + 1] = offset[j * g.ncol + C1] - a;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    rowpref[0] = 0;
+    for (int r = 1; r <= kTZ; ++r) rowpref[r] += rowpref[r - 1];
+  }
+  __syncthreads();
+  const int total = rowpref[kTZ];
+  const double zmin = st->zmin;
+  const double dt = g.dt;
+  int f0 = 0, f1 = total;
+  if (nchunk[t] != 1) {
+    f0 = chunk * tg.chunk;
+    f1 = min(total, f0 + tg.chunk);
+  }
+  {
+    // cells of the work item, their runs of at most kRun, and the exclusive
+    // prefix of the run counts
+    static_assert(kCells % 256 == 0 && kCells <= 512, "tile cells per thread");
+    constexpr int per = kCells / 256;
+    int nrun[per], tot = 0;
+#pragma unroll
+    for (int qq = 0; qq < per; ++qq) {
+      const int c = tid * per + qq;
+      const int row = c / TR, col = c % TR;
+      int lo = 0, hi = 0;
+      if (C0 + col < C1) {
+        const int* o = offset + (J0 + row) * g.ncol + C0 + col;
+        lo = max(f0, rowpref[row] + (o[0] - rowstart[row]));
+        hi = min(f1, rowpref[row] + (o[1] - rowstart[row]));
+      }
+      const int n = hi > lo ? hi - lo : 0;
+      cfirst[c] = rowstart[row] + (lo - rowpref[row]);
+      ccount[c] = n;
+      nrun[qq] = (n + kRun - 1) / kRun;
+      tot += nrun[qq];
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+    int inc = tot;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += u;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    int excl = inc - tot;
+    for (int w = 0; w < wave; ++w) excl += wsum[w];
+#pragma unroll
+    for (int qq = 0; qq < per; ++qq) {
+      runpref[tid * per + qq] = (uint16_t)excl;
+      excl += nrun[qq];
+    }
+    if (tid == 255) runpref[kCells] = (uint16_t)excl;
+    __syncthreads();
+  }
+  const int nruns = runpref[kCells];
+  const int q = tid & (kLPR - 1);
+  const int lane = tid & 63, gbase = lane & ~(kLPR - 1);
+  // lane q of the group taking run r: the sorted index of its first particle
+  // (q of the run; the others follow kLPR apart), how many of its kPPL
+  // particles exist, and the run's cell key (kInvalidKey past the last run)
+  auto slot_of = [&](int r, int& idx, int& cnt, uint32_t& key) {
+    idx = 0;
+    cnt = 0;
+    key = kInvalidKey;
+    if (r >= nruns) return;
+    int lo = 0, hi = kCells;   // runpref[lo] <= r < runpref[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if ((int)runpref[mid] <= r) lo = mid;
+      else hi = mid;
+    }
+    const int k = (r - (int)runpref[lo]) * kRun + q;
+    const int left = ccount[lo] - k;   // particles of the cell from this lane's first on
+    cnt = left <= 0 ? 0 : min(kPPL, (left + kLPR - 1) / kLPR);
+    idx = cfirst[lo] + k;
+    key = (uint32_t)(J0 + lo / TR) * 2048u + (uint32_t)(C0 + lo % TR);
+  };
+  int nidx, ncnt;
+  uint32_t nkey;
+  slot_of(tid / kLPR, nidx, ncnt, nkey);
+  PLoad nx[kPPL];
+#pragma unroll
+  for (int h = 0; h < kPPL; ++h)
+    if (h < ncnt) nx[h].load(p, nidx + h * kLPR);
+  for (int r0 = 0; r0 < nruns; r0 += kGroups) {
+    const int cnt = ncnt;
+    const uint32_t rkey = nkey;
+    PLoad cur[kPPL];
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) cur[h] = nx[h];
+    if (r0 + kGroups < nruns) {
+      slot_of(r0 + kGroups + tid / kLPR, nidx, ncnt, nkey);
+#pragma unroll
+      for (int h = 0; h < kPPL; ++h)
+        if (h < ncnt) nx[h].load(p, nidx + h * kLPR);
+    }
+    LanePart<M> P[kPPL];
+    bool inA[kPPL];
+    uint32_t outA[kPPL];
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) {
+      const bool valid = h < cnt;
+      double x = 0.0, y = 0.0, z = zmin;
+      float ux = 0.f, uy = 0.f, uz = 0.f, qw = 0.f;
+      if (valid) {
+        x = cur[h].x;
+        y = cur[h].y;
+        z = cur[h].z;
+        ux = cur[h].ux;
+        uy = cur[h].uy;
+        uz = (float)cur[h].uz;
+        qw = cur[h].w;
+      }
+      const float ginv = 1.f / sqrtf(1.f + ux * ux + uy * uy + uz * uz);
+      const float vx = ux * ginv, vy = uy * ginv, vz = uz * ginv;
+      // rho^{n+1} at x^{n+1}, in the run's cell (particles beyond the last
+      // radial node share the last key column and deposit nothing)
+      P[h].s = shape_at(x, y, z, zmin, g);
+      RS::values(valid && P[h].s.i0 < g.nr ? qw : 0.f, P[h].s.eith, P[h].vr);
+      // J^{n+1/2} at x^{n+1/2} = x^{n+1} - dt v / 2
+      P[h].sh = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy, z - 0.5 * dt * (double)vz, zmin, g);
+      P[h].kh = pos_key(P[h].sh, g.nr);
+      JS::values(qw, vx, vy, vz, P[h].sh.eith, P[h].vj);
+      inA[h] = !valid || P[h].kh == rkey;
+      outA[h] = (uint32_t)(__ballot(!inA[h]) >> gbase) & kGroupMask;
+    }
+    // the group's second J cell: that of its first particle outside the run's
+    // cell, in lane order, then particle order
+    uint32_t any = 0;
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) any |= outA[h];
+    const int first = any ? __ffs(any) - 1 : 0;
+    uint32_t kB = kInvalidKey;
+    {
+      bool taken = false;
+#pragma unroll
+      for (int h = 0; h < kPPL; ++h) {
+        const uint32_t kk = (uint32_t)__shfl((int)P[h].kh, gbase + first, 64);
+        if (!taken && ((outA[h] >> first) & 1u)) {
+          kB = kk;
+          taken = true;
+        }
+      }
+    }
+    bool inB[kPPL];
+    bool anyB = false;
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) {
+      inB[h] = !inA[h] && P[h].kh == kB;
+      anyB = anyB || inB[h];
+      if (!inA[h] && !inB[h]) {
+        // a third cell in the group: this particle's own atomics
+        const ShapePos& sh = P[h].sh;
+        Acc<JS::K> R;
+        R.key = P[h].kh;
+        const float jz[4] = {(1.f - sh.fz) * (1.f - sh.fr), sh.fz * (1.f - sh.fr), (1.f - sh.fz) * sh.fr,
+                             sh.fz * sh.fr};
+#pragma unroll
+        for (int k = 0; k < JS::K; ++k)
+#pragma unroll
+          for (int n = 0; n < 4; ++n) R.a[4 * k + n] = jz[n] * P[h].vj[k];
+        acc_flush<TR, H, JS::K, JS>(lds, R, g, J0, C0, [](int k) { return JS::off(k); });
+      }
+    }
+    {
+      float X[EA];
+#pragma unroll
+      for (int e = 0; e < EA; ++e) X[e] = 0.f;
+#pragma unroll
+      for (int h = 0; h < kPPL; ++h) {
+        const ShapePos& s = P[h].s;
+        const ShapePos& sh = P[h].sh;
+        const float rz[4] = {(1.f - s.fz) * (1.f - s.fr), s.fz * (1.f - s.fr), (1.f - s.fz) * s.fr, s.fz * s.fr};
+        const float fa = inA[h] ? 1.f : 0.f;
+        const float jz[4] = {fa * (1.f - sh.fz) * (1.f - sh.fr), fa * sh.fz * (1.f - sh.fr),
+                             fa * (1.f - sh.fz) * sh.fr, fa * sh.fz * sh.fr};
+#pragma unroll
+        for (int k = 0; k < RS::K; ++k)
+#pragma unroll
+          for (int n = 0; n < 4; ++n) X[4 * k + n] = fmaf(rz[n], P[h].vr[k], X[4 * k + n]);
+#pragma unroll
+        for (int k = 0; k < JS::K; ++k)
+#pragma unroll
+          for (int n = 0; n < 4; ++n) X[4 * RS::K + 4 * k + n] = fmaf(jz[n], P[h].vj[k], X[4 * RS::K + 4 * k + n]);
+      }
+      reduce_scatter(X, q);
+      if (rkey != kInvalidKey) flush_block<TR, H, M, EA, true>(lds, X, rkey, g, J0, C0, q);
+    }
+    const uint64_t bmask = __ballot(anyB);
+    if (bmask) {   // uniform over the wavefront
+      float Y[EB];
+#pragma unroll
+      for (int e = 0; e < EB; ++e) Y[e] = 0.f;
+#pragma unroll
+      for (int h = 0; h < kPPL; ++h) {
+        const ShapePos& sh = P[h].sh;
+        const float fb = inB[h] ? 1.f : 0.f;
+        const float jz[4] = {fb * (1.f - sh.fz) * (1.f - sh.fr), fb * sh.fz * (1.f - sh.fr),
+                             fb * (1.f - sh.fz) * sh.fr, fb * sh.fz * sh.fr};
+#pragma unroll
+        for (int k = 0; k < JS::K; ++k)
+#pragma unroll
+          for (int n = 0; n < 4; ++n) Y[4 * k + n] = fmaf(jz[n], P[h].vj[k], Y[4 * k + n]);
+      }
+      reduce_scatter(Y, q);
+      if ((bmask >> gbase) & kGroupMask) flush_block<TR, H, M, EB, false>(lds, Y, kB, g, J0, C0, q);
+    }
+  }
+  __syncthreads();
+  constexpr int nr_vals = RhoVals<M>::N;
+  if (ionblk && chunk == 0) {
+    // the tile's background, once per tile, in FP64, into rho^{n+1}
+    const double* src = ionblk + (size_t)t * nr_vals * B::NODES;
+    for (int e = tid; e < nr_vals * B::NODES; e += blockDim.x) {
+      const int k = e / B::NODES, node = e % B::NODES;
+      lds[RS::off(4, k) + node] += src[e];
+    }
+    __syncthreads();
+  }
+  float* dst = scratch + (size_t)b * nacc;
+  for (int e = tid; e < nacc; e += blockDim.x) dst[e] = (float)lds[e];
+}
+
 // Set-up of the background blocks: the FP64 rho slots of a tile's work items
 // (the chunks of a dense tile) are summed into the tile's block.
 template <int TR, int H, int M>
@@ -1030,8 +1405,18 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
       hipLaunchKernelGGL((k_deposit<TR, H, M, kDepFull, SHAPE>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
                          chunk_start, (float*)scratch, ionblk, g, tg, st);
     } else {
-      hipLaunchKernelGGL((k_deposit<TR, H, M, kDepCarry, SHAPE>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
-                         chunk_start, (float*)scratch, ionblk, g, tg, st);
+      if constexpr (SHAPE == 1 && M <= 2) {
+        static bool attr_lanes = false;
+        if (!attr_lanes) {
+          if (!set_lds_limit(k_deposit_lanes<TR, H, M>, lds)) return;
+          attr_lanes = true;
+        }
+        hipLaunchKernelGGL((k_deposit_lanes<TR, H, M>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
+                           chunk_start, (float*)scratch, ionblk, g, tg, st);
+      } else {
+        hipLaunchKernelGGL((k_deposit<TR, H, M, kDepCarry, SHAPE>), dim3(d.max_items), dim3(256), lds, s, p, offset,
+                           nchunk, chunk_start, (float*)scratch, ionblk, g, tg, st);
+      }
       if (rho_mode == kRhoCarryShift)
         hipLaunchKernelGGL((k_deposit<TR, H, M, kDepEdgeRho, SHAPE>), dim3(2 * d.ntr), dim3(256), lds, s, p, offset, nchunk,
                            chunk_start, (float*)scratch, ionblk, g, tg, st);
