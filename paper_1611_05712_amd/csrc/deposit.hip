@@ -805,20 +805,21 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
 
 // ---------------------------------------------------------------------------
 // Steady-state deposit (J^{n+1/2} and rho^{n+1}; rho^n carried over), linear
-// shapes: kLPR lanes per run of at most kRun particles of one cell, lane q
-// taking particles q, q + kLPR, ... of it.  The runs of a round are
-// consecutive in memory, so a wavefront's loads stay within a few lines.  A
-// lane sums its particles' node contributions in registers, the group then
-// sums over its lanes by a reduce-scatter (exchange steps inside the group,
-// each halving what a lane keeps), after which lane q holds the sums of the
-// q-th block of entries and issues their FP64 LDS atomics.
+// shapes: four lanes per run of at most kRun particles of one cell, lane q
+// taking particles q and q + 4 of it.  The runs of a round are consecutive in
+// memory, so a wavefront's loads stay within a few lines.  A lane sums its
+// particles' node contributions in registers, node-major (entry n K + k: value
+// k at node n of the cell), and the four lanes then sum over the group by a
+// reduce-scatter (two exchange steps, each halving what a lane keeps), after
+// which lane q holds every value of node q and issues their FP64 LDS atomics
+// at offsets known at compile time.
 //   * rho^{n+1}: every particle of a run is in the run's cell;
 //   * J^{n+1/2}: particles whose half-step cell is the run's cell join its
 //     sums; of the others, those in the cell of the group's first such
 //     particle are summed into a second set; any further cell deposits
 //     particle by particle.
 // ---------------------------------------------------------------------------
-constexpr int kLPR = 4;              // lanes per run
+constexpr int kLPR = 4;              // lanes per run: one per node of the cell
 constexpr int kPPL = kRun / kLPR;    // particles per lane and run
 
 template <int CTRL>
@@ -840,67 +841,49 @@ __device__ __forceinline__ void rs_step(float (&a)[CAP], bool up) {
   }
 }
 
-// sum over the kLPR lanes of a group; afterwards lane q holds the sums of
-// entries q*N/kLPR .. (q+1)*N/kLPR - 1 in a[0 .. N/kLPR)
+// sum over the four lanes of a group; afterwards lane q holds the sums of
+// entries q*N/4 .. (q+1)*N/4 - 1 in a[0 .. N/4)
 template <int N>
-__device__ __forceinline__ void reduce_scatter(float (&a)[N], int q) {
-  static_assert(N % kLPR == 0, "entries per group lane");
-  if constexpr (kLPR == 8) {
-    rs_step<N, 0x141>(a, (q & 4) != 0);   // partner q ^ 7 (mirror within eight lanes)
-    rs_step<N / 2, 0x4E>(a, (q & 2) != 0);   // partner q ^ 2
-    rs_step<N / 4, 0xB1>(a, (q & 1) != 0);   // partner q ^ 1
-  } else {
-    static_assert(kLPR == 4, "four or eight lanes per run");
-    rs_step<N, 0x4E>(a, (q & 2) != 0);
-    rs_step<N / 2, 0xB1>(a, (q & 1) != 0);
-  }
+__device__ __forceinline__ void reduce_scatter4(float (&a)[N], int q) {
+  static_assert(N % 4 == 0 && kLPR == 4, "four lanes per run, whole nodes per lane");
+  rs_step<N, 0x4E>(a, (q & 2) != 0);       // partner q ^ 2: nodes 0, 1 or 2, 3
+  rs_step<N / 2, 0xB1>(a, (q & 1) != 0);   // partner q ^ 1: node q
 }
 
-__host__ __device__ constexpr int pad_lpr(int n) { return (n + kLPR - 1) / kLPR * kLPR; }
-
-// FP64 LDS atomics of lane q's block of entries of a reduced set.  Entry
-// e = 4 k + n is value k (rho^{n+1} values first when kRho) at node n of the
-// cell `key`: n = 0, 1 the inner radial node at j0, j0 + 1; n = 2, 3 the
-// outer one.
-template <int TR, int H, int M, int N, bool kRho>
-__device__ __forceinline__ void flush_block(double* __restrict__ lds, const float (&a)[N], uint32_t key,
-                                           const Grid& g, int J0, int C0, int q) {
+// FP64 LDS atomics of node q of the cell `key` (q = 0, 1: the inner radial
+// node at j0, j0 + 1; q = 2, 3: the outer one) from lane q's reduced values
+// a[0 .. KN): the rho^{n+1} values first when kRho, then the J values.
+template <int TR, int H, int M, bool kRho, int N>
+__device__ __forceinline__ void flush_node(double* __restrict__ lds, const float (&a)[N], uint32_t key,
+                                          const Grid& g, int J0, int C0, int q) {
   using B = Blk<TR, H>;
   using RS = RhoSet<M, B::NODES>;
   using JS = JSet<M, B::NODES>;
-  constexpr int NR = kRho ? 4 * RS::K : 0;
-  constexpr int NE = NR + 4 * JS::K;
+  constexpr int NR = kRho ? RS::K : 0;
+  constexpr int KN = NR + JS::K;
+  static_assert(N == 4 * KN, "node-major entries");
   ShapePos s;
   s.j0 = (int)(key >> 11);
   s.i0 = (int)(key & 2047u) - 1;
   const Local<TR, H> L = localize<TR, H>(s, g, J0, C0);
+  const bool outer = q >= 2;
+  if ((outer ? L.sb : L.sa_even) == 0.f) return;
+  double* __restrict__ base = lds + (outer ? L.nb : L.na) + (q & 1);
+  const float sg = outer ? 1.f : L.sa_odd;   // -1 on the ghost node across the axis (odd Hankel orders)
 #pragma unroll
-  for (int i = 0; i < N / kLPR; ++i) {
-    const int e = q * (N / kLPR) + i;
-    if (e >= NE) continue;
-    int off, par;
-    if (kRho && e < NR) {
-      off = RS::off(4, e >> 2);
-      par = RS::parity(e >> 2);
-    } else {
-      off = JS::off((e - NR) >> 2);
-      par = JS::parity((e - NR) >> 2);
-    }
-    const int n = e & 3;
-    if (n < 2) {
-      if (L.sa_even != 0.f) atomicAdd(lds + L.na + off + n, (double)(par ? L.sa_odd * a[i] : a[i]));
-    } else if (L.sb != 0.f) {
-      atomicAdd(lds + L.nb + off + (n - 2), (double)a[i]);
-    }
+  for (int k = 0; k < KN; ++k) {
+    const bool rho = kRho && k < NR;
+    const int off = rho ? RS::off(4, k) : JS::off(k - NR);
+    const bool par = rho ? RS::parity(k) : JS::parity(k - NR);
+    atomicAdd(base + off, (double)(par ? sg * a[k] : a[k]));
   }
 }
 
-// one particle's shape data for the lane-group deposit
+// what a particle keeps for the second J cell and the lane-by-lane atomics
 template <int M>
-struct LanePart {
-  ShapePos s, sh;          // x^{n+1}, x^{n+1/2}
+struct LaneJ {
+  float fz, fr;            // x^{n+1/2} within its cell
   uint32_t kh;             // cell key of x^{n+1/2}
-  float vr[1 + 2 * (M - 1)];
   float vj[3 + 6 * (M - 1)];
 };
 
@@ -917,8 +900,8 @@ __global__ __launch_bounds__(256) void k_deposit_lanes(Parts p, const int* __res
   constexpr int nacc = Vals<M>::N * B::NODES;
   constexpr int kCells = kTZ * TR;
   constexpr int kGroups = 256 / kLPR;          // runs per round
-  constexpr int EA = pad_lpr(4 * (RS::K + JS::K));
-  constexpr int EB = pad_lpr(4 * JS::K);
+  constexpr int KA = RS::K + JS::K;          // values per node, run cell
+  constexpr int KB = JS::K;                  // values per node, second J cell
   constexpr uint32_t kGroupMask = (1u << kLPR) - 1u;
   __shared__ int rowstart[kTZ];
   __shared__ int rowpref[kTZ + 1];
@@ -1051,7 +1034,12 @@ __global__ __launch_bounds__(256) void k_deposit_lanes(Parts p, const int* __res
       for (int h = 0; h < kPPL; ++h)
         if (h < ncnt) nx[h].load(p, nidx + h * kLPR);
     }
-    LanePart<M> P[kPPL];
+    // the run's cell: rho^{n+1} of every particle, J of those whose x^{n+1/2}
+    // is in it; summed in registers over the lane's particles
+    float X[4 * KA];
+#pragma unroll
+    for (int e = 0; e < 4 * KA; ++e) X[e] = 0.f;
+    LaneJ<M> P[kPPL];
     bool inA[kPPL];
     uint32_t outA[kPPL];
 #pragma unroll
@@ -1072,15 +1060,33 @@ __global__ __launch_bounds__(256) void k_deposit_lanes(Parts p, const int* __res
       const float vx = ux * ginv, vy = uy * ginv, vz = uz * ginv;
       // rho^{n+1} at x^{n+1}, in the run's cell (particles beyond the last
       // radial node share the last key column and deposit nothing)
-      P[h].s = shape_at(x, y, z, zmin, g);
-      RS::values(valid && P[h].s.i0 < g.nr ? qw : 0.f, P[h].s.eith, P[h].vr);
+      const ShapePos s = shape_at(x, y, z, zmin, g);
+      float vr[RS::K];
+      RS::values(valid && s.i0 < g.nr ? qw : 0.f, s.eith, vr);
       // J^{n+1/2} at x^{n+1/2} = x^{n+1} - dt v / 2
-      P[h].sh = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy, z - 0.5 * dt * (double)vz, zmin, g);
-      P[h].kh = pos_key(P[h].sh, g.nr);
-      JS::values(qw, vx, vy, vz, P[h].sh.eith, P[h].vj);
+      const ShapePos sh = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy,
+                                   z - 0.5 * dt * (double)vz, zmin, g);
+      P[h].fz = sh.fz;
+      P[h].fr = sh.fr;
+      P[h].kh = pos_key(sh, g.nr);
+      JS::values(qw, vx, vy, vz, sh.eith, P[h].vj);
       inA[h] = !valid || P[h].kh == rkey;
       outA[h] = (uint32_t)(__ballot(!inA[h]) >> gbase) & kGroupMask;
+      const float rz[4] = {(1.f - s.fz) * (1.f - s.fr), s.fz * (1.f - s.fr), (1.f - s.fz) * s.fr, s.fz * s.fr};
+      const float fa = inA[h] ? 1.f : 0.f;
+      const float jz[4] = {fa * (1.f - sh.fz) * (1.f - sh.fr), fa * sh.fz * (1.f - sh.fr),
+                           fa * (1.f - sh.fz) * sh.fr, fa * sh.fz * sh.fr};
+#pragma unroll
+      for (int k = 0; k < RS::K; ++k)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) X[n * KA + k] = fmaf(rz[n], vr[k], X[n * KA + k]);
+#pragma unroll
+      for (int k = 0; k < JS::K; ++k)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) X[n * KA + RS::K + k] = fmaf(jz[n], P[h].vj[k], X[n * KA + RS::K + k]);
     }
+    reduce_scatter4(X, q);
+    if (rkey != kInvalidKey) flush_node<TR, H, M, true>(lds, X, rkey, g, J0, C0, q);
     // the group's second J cell: that of its first particle outside the run's
     // cell, in lane order, then particle order
     uint32_t any = 0;
@@ -1107,11 +1113,10 @@ __global__ __launch_bounds__(256) void k_deposit_lanes(Parts p, const int* __res
       anyB = anyB || inB[h];
       if (!inA[h] && !inB[h]) {
         // a third cell in the group: this particle's own atomics
-        const ShapePos& sh = P[h].sh;
         Acc<JS::K> R;
         R.key = P[h].kh;
-        const float jz[4] = {(1.f - sh.fz) * (1.f - sh.fr), sh.fz * (1.f - sh.fr), (1.f - sh.fz) * sh.fr,
-                             sh.fz * sh.fr};
+        const float fz = P[h].fz, fr = P[h].fr;
+        const float jz[4] = {(1.f - fz) * (1.f - fr), fz * (1.f - fr), (1.f - fz) * fr, fz * fr};
 #pragma unroll
         for (int k = 0; k < JS::K; ++k)
 #pragma unroll
@@ -1119,48 +1124,23 @@ __global__ __launch_bounds__(256) void k_deposit_lanes(Parts p, const int* __res
         acc_flush<TR, H, JS::K, JS>(lds, R, g, J0, C0, [](int k) { return JS::off(k); });
       }
     }
-    {
-      float X[EA];
-#pragma unroll
-      for (int e = 0; e < EA; ++e) X[e] = 0.f;
-#pragma unroll
-      for (int h = 0; h < kPPL; ++h) {
-        const ShapePos& s = P[h].s;
-        const ShapePos& sh = P[h].sh;
-        const float rz[4] = {(1.f - s.fz) * (1.f - s.fr), s.fz * (1.f - s.fr), (1.f - s.fz) * s.fr, s.fz * s.fr};
-        const float fa = inA[h] ? 1.f : 0.f;
-        const float jz[4] = {fa * (1.f - sh.fz) * (1.f - sh.fr), fa * sh.fz * (1.f - sh.fr),
-                             fa * (1.f - sh.fz) * sh.fr, fa * sh.fz * sh.fr};
-#pragma unroll
-        for (int k = 0; k < RS::K; ++k)
-#pragma unroll
-          for (int n = 0; n < 4; ++n) X[4 * k + n] = fmaf(rz[n], P[h].vr[k], X[4 * k + n]);
-#pragma unroll
-        for (int k = 0; k < JS::K; ++k)
-#pragma unroll
-          for (int n = 0; n < 4; ++n) X[4 * RS::K + 4 * k + n] = fmaf(jz[n], P[h].vj[k], X[4 * RS::K + 4 * k + n]);
-      }
-      reduce_scatter(X, q);
-      if (rkey != kInvalidKey) flush_block<TR, H, M, EA, true>(lds, X, rkey, g, J0, C0, q);
-    }
     const uint64_t bmask = __ballot(anyB);
     if (bmask) {   // uniform over the wavefront
-      float Y[EB];
+      float Y[4 * KB];
 #pragma unroll
-      for (int e = 0; e < EB; ++e) Y[e] = 0.f;
+      for (int e = 0; e < 4 * KB; ++e) Y[e] = 0.f;
 #pragma unroll
       for (int h = 0; h < kPPL; ++h) {
-        const ShapePos& sh = P[h].sh;
+        const float fz = P[h].fz, fr = P[h].fr;
         const float fb = inB[h] ? 1.f : 0.f;
-        const float jz[4] = {fb * (1.f - sh.fz) * (1.f - sh.fr), fb * sh.fz * (1.f - sh.fr),
-                             fb * (1.f - sh.fz) * sh.fr, fb * sh.fz * sh.fr};
+        const float jz[4] = {fb * (1.f - fz) * (1.f - fr), fb * fz * (1.f - fr), fb * (1.f - fz) * fr, fb * fz * fr};
 #pragma unroll
         for (int k = 0; k < JS::K; ++k)
 #pragma unroll
-          for (int n = 0; n < 4; ++n) Y[4 * k + n] = fmaf(jz[n], P[h].vj[k], Y[4 * k + n]);
+          for (int n = 0; n < 4; ++n) Y[n * KB + k] = fmaf(jz[n], P[h].vj[k], Y[n * KB + k]);
       }
-      reduce_scatter(Y, q);
-      if ((bmask >> gbase) & kGroupMask) flush_block<TR, H, M, EB, false>(lds, Y, kB, g, J0, C0, q);
+      reduce_scatter4(Y, q);
+      if ((bmask >> gbase) & kGroupMask) flush_node<TR, H, M, false>(lds, Y, kB, g, J0, C0, q);
     }
   }
   __syncthreads();
