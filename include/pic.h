@@ -402,8 +402,9 @@ int pic_step_graph(pic_ctx* ctx, int n);
  * timing off.  Same results as pic_step to rounding.  Errors: PIC_ESTATE,
  * PIC_EINVAL, PIC_EHIP (steps already enqueued stay enqueued).
  *
- * pic_batch_free: waits for the batch's replays, then releases the graph,
- * events and lead stream (not the contexts).  Errors: PIC_EINVAL, PIC_EHIP. */
+ * pic_batch_free: waits for the batch's replays and for the work queued on
+ * every context's stream, then releases the graph, events and lead stream
+ * (not the contexts).  Errors: PIC_EINVAL, PIC_EHIP. */
 typedef struct pic_batch pic_batch;
 int pic_batch_create(pic_ctx* const* ctxs, int n_ctx, pic_batch** out);
 int pic_batch_run(pic_batch* batch, int n);

@@ -1283,6 +1283,10 @@ int batch_capture(pic_batch* b) {
     (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
   }
+  // the events are recorded again inside the capture: first let the waits the
+  // context streams still hold on their earlier records complete
+  for (pic_ctx* x : b->ctx)
+    if (hipStreamSynchronize(x->stream) != hipSuccess) return PIC_EHIP;
   const size_t n = b->ctx.size();
   std::vector<HostMirror> saved(n);
   for (size_t i = 0; i < n; ++i) saved[i] = save_mirror(b->ctx[i]);
@@ -1407,6 +1411,11 @@ int pic_batch_free(pic_batch* b) {
   if (!b) return PIC_EINVAL;
   int rc = PIC_OK;
   if (b->lead && hipStreamSynchronize(b->lead) != hipSuccess) rc = PIC_EHIP;
+  // every context's stream holds a wait on the lead event after the replays:
+  // let those waits complete before the event and the lead stream they refer
+  // to are destroyed
+  for (pic_ctx* x : b->ctx)
+    if (hipStreamSynchronize(x->stream) != hipSuccess) rc = PIC_EHIP;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->ev_lead) (void)hipEventDestroy(b->ev_lead);
   for (hipEvent_t e : b->ev_ctx)
