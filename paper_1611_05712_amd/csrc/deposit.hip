@@ -850,17 +850,34 @@ __device__ __forceinline__ void reduce_scatter4(float (&a)[N], int q) {
   rs_step<N / 2, 0xB1>(a, (q & 1) != 0);   // partner q ^ 1: node q
 }
 
+// The position kinds of the lane-group kernel.  kDepCarry: rho^{n+1} at
+// x^{n+1} (always the run's cell) and the split set J^{n+1/2} at x^{n+1/2};
+// kDepEdgeRho: only the split set rho^n at x^n.
+template <int M, int NODES, int MODE>
+struct LaneSets {
+  using RS = RhoSet<M, NODES>;
+  using JS = JSet<M, NODES>;
+  static constexpr bool kEdge = MODE == kDepEdgeRho;
+  static constexpr int KR = kEdge ? 0 : RS::K;   // values that always go to the run's cell
+  static constexpr int KS = kEdge ? RS::K : JS::K;   // values of the split set
+  static __device__ __forceinline__ constexpr int split_off(int k) { return kEdge ? RS::off(3, k) : JS::off(k); }
+  static __device__ __forceinline__ constexpr int split_parity(int k) {
+    return kEdge ? RS::parity(k) : JS::parity(k);
+  }
+};
+
 // FP64 LDS atomics of node q of the cell `key` (q = 0, 1: the inner radial
 // node at j0, j0 + 1; q = 2, 3: the outer one) from lane q's reduced values
-// a[0 .. KN): the rho^{n+1} values first when kRho, then the J values.
-template <int TR, int H, int M, bool kRho, int N>
+// a[0 .. KN): the values that always go to the run's cell first when
+// kAlways, then those of the split set.
+template <int TR, int H, int M, int MODE, bool kAlways, int N>
 __device__ __forceinline__ void flush_node(double* __restrict__ lds, const float (&a)[N], uint32_t key,
                                           const Grid& g, int J0, int C0, int q) {
   using B = Blk<TR, H>;
   using RS = RhoSet<M, B::NODES>;
-  using JS = JSet<M, B::NODES>;
-  constexpr int NR = kRho ? RS::K : 0;
-  constexpr int KN = NR + JS::K;
+  using LS = LaneSets<M, B::NODES, MODE>;
+  constexpr int NR = kAlways ? LS::KR : 0;
+  constexpr int KN = NR + LS::KS;
   static_assert(N == 4 * KN, "node-major entries");
   ShapePos s;
   s.j0 = (int)(key >> 11);
@@ -872,64 +889,78 @@ __device__ __forceinline__ void flush_node(double* __restrict__ lds, const float
   const float sg = outer ? 1.f : L.sa_odd;   // -1 on the ghost node across the axis (odd Hankel orders)
 #pragma unroll
   for (int k = 0; k < KN; ++k) {
-    const bool rho = kRho && k < NR;
-    const int off = rho ? RS::off(4, k) : JS::off(k - NR);
-    const bool par = rho ? RS::parity(k) : JS::parity(k - NR);
+    const bool always = k < NR;
+    const int off = always ? RS::off(4, k) : LS::split_off(k - NR);
+    const bool par = always ? RS::parity(k) : LS::split_parity(k - NR);
     atomicAdd(base + off, (double)(par ? sg * a[k] : a[k]));
   }
 }
 
-// what a particle keeps for the second J cell and the lane-by-lane atomics
-template <int M>
-struct LaneJ {
-  float fz, fr;            // x^{n+1/2} within its cell
-  uint32_t kh;             // cell key of x^{n+1/2}
-  float vj[3 + 6 * (M - 1)];
+// what a particle keeps of its split-set position for the second cell and
+// the particle-by-particle atomics
+template <int K>
+struct LaneSplit {
+  float fz, fr;            // position within its cell
+  uint32_t key;            // its cell key
+  float v[K];
 };
 
-template <int TR, int H, int M>
-__global__ __launch_bounds__(256) void k_deposit_lanes(Parts p, const int* __restrict__ offset,
-                                                       const int* __restrict__ nchunk,
-                                                       const int* __restrict__ chunk_start,
-                                                       float* __restrict__ scratch, const double* __restrict__ ionblk,
-                                                       Grid g, TileGeom tg, DevState* st) {
+// kDepCarry: one workgroup per work item (NT = 256), the slot written whole.
+// kDepEdgeRho: one workgroup per tile of the two tile rows at the window ends
+// (all of its particles, in pieces of one chunk), rho^n written into the rho^n
+// part of the tile's first slot.
+template <int TR, int H, int M, int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_deposit_lanes(Parts p, const int* __restrict__ offset,
+                                                      const int* __restrict__ nchunk,
+                                                      const int* __restrict__ chunk_start,
+                                                      float* __restrict__ scratch, const double* __restrict__ ionblk,
+                                                      Grid g, TileGeom tg, DevState* st) {
   using B = Blk<TR, H>;
   using RS = RhoSet<M, B::NODES>;
   using JS = JSet<M, B::NODES>;
+  using LS = LaneSets<M, B::NODES, MODE>;
+  static_assert(MODE == kDepCarry || MODE == kDepEdgeRho, "steady-state modes");
+  constexpr bool kEdge = LS::kEdge;
   extern __shared__ double lds[];
   constexpr int nacc = Vals<M>::N * B::NODES;
   constexpr int kCells = kTZ * TR;
-  constexpr int kGroups = 256 / kLPR;          // runs per round
-  constexpr int KA = RS::K + JS::K;          // values per node, run cell
-  constexpr int KB = JS::K;                  // values per node, second J cell
+  constexpr int kWaves = NT / 64;
+  constexpr int kGroups = NT / kLPR;          // runs per round
+  constexpr int KA = LS::KR + LS::KS;         // values per node, run cell
+  constexpr int KB = LS::KS;                  // values per node, second cell
   constexpr uint32_t kGroupMask = (1u << kLPR) - 1u;
   __shared__ int rowstart[kTZ];
   __shared__ int rowpref[kTZ + 1];
   __shared__ uint16_t runpref[kCells + 1];
-  __shared__ int cfirst[kCells];   // sorted index of each cell's first particle (clipped to the work item)
-  __shared__ int ccount[kCells];   // its particles in the work item
-  __shared__ int wsum[4];
+  __shared__ int cfirst[kCells];   // sorted index of each cell's first particle (clipped to the piece)
+  __shared__ int ccount[kCells];   // its particles in the piece
+  __shared__ int wsum[kWaves];
   __shared__ int s_tile;
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
-  if (b == 0 && tid == 0) {
-    st->n_part = st->n_live;
-    if (chunk_start[tg.ntiles] > (int)gridDim.x) st->overflow = 2;   // work list larger than the launch
-  }
-  if (b >= chunk_start[tg.ntiles]) return;   // uniform per workgroup
-  if (tid == 0) {
-    int lo = 0, hi = tg.ntiles;   // chunk_start[lo] <= b < chunk_start[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (chunk_start[mid] <= b) lo = mid;
-      else hi = mid;
+  if (kEdge) {
+    // edge tiles: tz = 0 and tz = ntz - 1 of every radial tile column
+    if (tid == 0) s_tile = (b >> 1) * tg.ntz + ((b & 1) ? tg.ntz - 1 : 0);
+  } else {
+    if (b == 0 && tid == 0) {
+      st->n_part = st->n_live;
+      if (chunk_start[tg.ntiles] > (int)gridDim.x) st->overflow = 2;   // work list larger than the launch
     }
-    s_tile = lo;
+    if (b >= chunk_start[tg.ntiles]) return;   // uniform per workgroup
+    if (tid == 0) {
+      int lo = 0, hi = tg.ntiles;   // chunk_start[lo] <= b < chunk_start[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (chunk_start[mid] <= b) lo = mid;
+        else hi = mid;
+      }
+      s_tile = lo;
+    }
   }
-  for (int e = tid; e < nacc; e += blockDim.x) lds[e] = 0.0;
+  for (int e = tid; e < nacc; e += NT) lds[e] = 0.0;
   __syncthreads();
   const int t = s_tile;
-  const int chunk = b - chunk_start[t];
+  const int chunk = kEdge ? 0 : b - chunk_start[t];
   const int J0 = (t % tg.ntz) * kTZ, C0 = (t / tg.ntz) * TR;
   const int C1 = min(C0 + TR, g.ncol);
   if (tid < kTZ) {
@@ -947,215 +978,247 @@ __global__ __launch_bounds__(256) void k_deposit_lanes(Parts p, const int* __res
   const int total = rowpref[kTZ];
   const double zmin = st->zmin;
   const double dt = g.dt;
+  const int npiece = kEdge ? max(1, (total + tg.chunk - 1) / tg.chunk) : 1;
   int f0 = 0, f1 = total;
-  if (nchunk[t] != 1) {
+  if (!kEdge && nchunk[t] != 1) {
     f0 = chunk * tg.chunk;
     f1 = min(total, f0 + tg.chunk);
   }
-  {
-    // cells of the work item, their runs of at most kRun, and the exclusive
-    // prefix of the run counts
-    static_assert(kCells % 256 == 0 && kCells <= 512, "tile cells per thread");
-    constexpr int per = kCells / 256;
-    int nrun[per], tot = 0;
-#pragma unroll
-    for (int qq = 0; qq < per; ++qq) {
-      const int c = tid * per + qq;
-      const int row = c / TR, col = c % TR;
-      int lo = 0, hi = 0;
-      if (C0 + col < C1) {
-        const int* o = offset + (J0 + row) * g.ncol + C0 + col;
-        lo = max(f0, rowpref[row] + (o[0] - rowstart[row]));
-        hi = min(f1, rowpref[row] + (o[1] - rowstart[row]));
-      }
-      const int n = hi > lo ? hi - lo : 0;
-      cfirst[c] = rowstart[row] + (lo - rowpref[row]);
-      ccount[c] = n;
-      nrun[qq] = (n + kRun - 1) / kRun;
-      tot += nrun[qq];
-    }
-    const int lane = tid & 63, wave = tid >> 6;
-    int inc = tot;
-    for (int d = 1; d < 64; d <<= 1) {
-      const int u = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += u;
-    }
-    if (lane == 63) wsum[wave] = inc;
-    __syncthreads();
-    int excl = inc - tot;
-    for (int w = 0; w < wave; ++w) excl += wsum[w];
-#pragma unroll
-    for (int qq = 0; qq < per; ++qq) {
-      runpref[tid * per + qq] = (uint16_t)excl;
-      excl += nrun[qq];
-    }
-    if (tid == 255) runpref[kCells] = (uint16_t)excl;
-    __syncthreads();
-  }
-  const int nruns = runpref[kCells];
   const int q = tid & (kLPR - 1);
   const int lane = tid & 63, gbase = lane & ~(kLPR - 1);
-  // lane q of the group taking run r: the sorted index of its first particle
-  // (q of the run; the others follow kLPR apart), how many of its kPPL
-  // particles exist, and the run's cell key (kInvalidKey past the last run)
-  auto slot_of = [&](int r, int& idx, int& cnt, uint32_t& key) {
-    idx = 0;
-    cnt = 0;
-    key = kInvalidKey;
-    if (r >= nruns) return;
-    int lo = 0, hi = kCells;   // runpref[lo] <= r < runpref[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if ((int)runpref[mid] <= r) lo = mid;
-      else hi = mid;
+  for (int piece = 0; piece < npiece; ++piece) {
+    if (kEdge) {
+      f0 = piece * tg.chunk;
+      f1 = min(total, f0 + tg.chunk);
     }
-    const int k = (r - (int)runpref[lo]) * kRun + q;
-    const int left = ccount[lo] - k;   // particles of the cell from this lane's first on
-    cnt = left <= 0 ? 0 : min(kPPL, (left + kLPR - 1) / kLPR);
-    idx = cfirst[lo] + k;
-    key = (uint32_t)(J0 + lo / TR) * 2048u + (uint32_t)(C0 + lo % TR);
-  };
-  int nidx, ncnt;
-  uint32_t nkey;
-  slot_of(tid / kLPR, nidx, ncnt, nkey);
-  PLoad nx[kPPL];
-#pragma unroll
-  for (int h = 0; h < kPPL; ++h)
-    if (h < ncnt) nx[h].load(p, nidx + h * kLPR);
-  for (int r0 = 0; r0 < nruns; r0 += kGroups) {
-    const int cnt = ncnt;
-    const uint32_t rkey = nkey;
-    PLoad cur[kPPL];
-#pragma unroll
-    for (int h = 0; h < kPPL; ++h) cur[h] = nx[h];
-    if (r0 + kGroups < nruns) {
-      slot_of(r0 + kGroups + tid / kLPR, nidx, ncnt, nkey);
-#pragma unroll
-      for (int h = 0; h < kPPL; ++h)
-        if (h < ncnt) nx[h].load(p, nidx + h * kLPR);
-    }
-    // the run's cell: rho^{n+1} of every particle, J of those whose x^{n+1/2}
-    // is in it; summed in registers over the lane's particles
-    float X[4 * KA];
-#pragma unroll
-    for (int e = 0; e < 4 * KA; ++e) X[e] = 0.f;
-    LaneJ<M> P[kPPL];
-    bool inA[kPPL];
-    uint32_t outA[kPPL];
-#pragma unroll
-    for (int h = 0; h < kPPL; ++h) {
-      const bool valid = h < cnt;
-      double x = 0.0, y = 0.0, z = zmin;
-      float ux = 0.f, uy = 0.f, uz = 0.f, qw = 0.f;
-      if (valid) {
-        x = cur[h].x;
-        y = cur[h].y;
-        z = cur[h].z;
-        ux = cur[h].ux;
-        uy = cur[h].uy;
-        uz = (float)cur[h].uz;
-        qw = cur[h].w;
-      }
-      const float ginv = 1.f / sqrtf(1.f + ux * ux + uy * uy + uz * uz);
-      const float vx = ux * ginv, vy = uy * ginv, vz = uz * ginv;
-      // rho^{n+1} at x^{n+1}, in the run's cell (particles beyond the last
-      // radial node share the last key column and deposit nothing)
-      const ShapePos s = shape_at(x, y, z, zmin, g);
-      float vr[RS::K];
-      RS::values(valid && s.i0 < g.nr ? qw : 0.f, s.eith, vr);
-      // J^{n+1/2} at x^{n+1/2} = x^{n+1} - dt v / 2
-      const ShapePos sh = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy,
-                                   z - 0.5 * dt * (double)vz, zmin, g);
-      P[h].fz = sh.fz;
-      P[h].fr = sh.fr;
-      P[h].kh = pos_key(sh, g.nr);
-      JS::values(qw, vx, vy, vz, sh.eith, P[h].vj);
-      inA[h] = !valid || P[h].kh == rkey;
-      outA[h] = (uint32_t)(__ballot(!inA[h]) >> gbase) & kGroupMask;
-      const float rz[4] = {(1.f - s.fz) * (1.f - s.fr), s.fz * (1.f - s.fr), (1.f - s.fz) * s.fr, s.fz * s.fr};
-      const float fa = inA[h] ? 1.f : 0.f;
-      const float jz[4] = {fa * (1.f - sh.fz) * (1.f - sh.fr), fa * sh.fz * (1.f - sh.fr),
-                           fa * (1.f - sh.fz) * sh.fr, fa * sh.fz * sh.fr};
-#pragma unroll
-      for (int k = 0; k < RS::K; ++k)
-#pragma unroll
-        for (int n = 0; n < 4; ++n) X[n * KA + k] = fmaf(rz[n], vr[k], X[n * KA + k]);
-#pragma unroll
-      for (int k = 0; k < JS::K; ++k)
-#pragma unroll
-        for (int n = 0; n < 4; ++n) X[n * KA + RS::K + k] = fmaf(jz[n], P[h].vj[k], X[n * KA + RS::K + k]);
-    }
-    reduce_scatter4(X, q);
-    if (rkey != kInvalidKey) flush_node<TR, H, M, true>(lds, X, rkey, g, J0, C0, q);
-    // the group's second J cell: that of its first particle outside the run's
-    // cell, in lane order, then particle order
-    uint32_t any = 0;
-#pragma unroll
-    for (int h = 0; h < kPPL; ++h) any |= outA[h];
-    const int first = any ? __ffs(any) - 1 : 0;
-    uint32_t kB = kInvalidKey;
+    __syncthreads();   // the previous piece's table is no longer read
     {
-      bool taken = false;
+      // cells of the piece, their runs of at most kRun, and the exclusive
+      // prefix of the run counts
+      static_assert(kCells % NT == 0 || NT % kCells == 0, "tile cells per thread");
+      constexpr int per = kCells >= NT ? kCells / NT : 1;
+      int nrun[per], tot = 0;
+#pragma unroll
+      for (int qq = 0; qq < per; ++qq) {
+        const int c = tid * per + qq;
+        nrun[qq] = 0;
+        if (c < kCells) {
+          const int row = c / TR, col = c % TR;
+          int lo = 0, hi = 0;
+          if (C0 + col < C1) {
+            const int* o = offset + (J0 + row) * g.ncol + C0 + col;
+            lo = max(f0, rowpref[row] + (o[0] - rowstart[row]));
+            hi = min(f1, rowpref[row] + (o[1] - rowstart[row]));
+          }
+          const int n = hi > lo ? hi - lo : 0;
+          cfirst[c] = rowstart[row] + (lo - rowpref[row]);
+          ccount[c] = n;
+          nrun[qq] = (n + kRun - 1) / kRun;
+        }
+        tot += nrun[qq];
+      }
+      const int wave = tid >> 6;
+      int inc = tot;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += u;
+      }
+      if (lane == 63) wsum[wave] = inc;
+      __syncthreads();
+      int excl = inc - tot;
+      for (int w = 0; w < wave; ++w) excl += wsum[w];
+#pragma unroll
+      for (int qq = 0; qq < per; ++qq) {
+        if (tid * per + qq < kCells) runpref[tid * per + qq] = (uint16_t)excl;
+        excl += nrun[qq];
+      }
+      if (tid == NT - 1) runpref[kCells] = (uint16_t)excl;
+      __syncthreads();
+    }
+    const int nruns = runpref[kCells];
+    // lane q of the group taking run r: the sorted index of its first
+    // particle (q of the run; the others follow kLPR apart), how many of its
+    // kPPL particles exist, and the run's cell key (kInvalidKey past the last
+    // run)
+    auto slot_of = [&](int r, int& idx, int& cnt, uint32_t& key) {
+      idx = 0;
+      cnt = 0;
+      key = kInvalidKey;
+      if (r >= nruns) return;
+      int lo = 0, hi = kCells;   // runpref[lo] <= r < runpref[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)runpref[mid] <= r) lo = mid;
+        else hi = mid;
+      }
+      const int k = (r - (int)runpref[lo]) * kRun + q;
+      const int left = ccount[lo] - k;   // particles of the cell from this lane's first on
+      cnt = left <= 0 ? 0 : min(kPPL, (left + kLPR - 1) / kLPR);
+      idx = cfirst[lo] + k;
+      key = (uint32_t)(J0 + lo / TR) * 2048u + (uint32_t)(C0 + lo % TR);
+    };
+    int nidx, ncnt;
+    uint32_t nkey;
+    slot_of(tid / kLPR, nidx, ncnt, nkey);
+    PLoad nx[kPPL];
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h)
+      if (h < ncnt) nx[h].load(p, nidx + h * kLPR);
+    for (int r0 = 0; r0 < nruns; r0 += kGroups) {
+      const int cnt = ncnt;
+      const uint32_t rkey = nkey;
+      PLoad cur[kPPL];
+#pragma unroll
+      for (int h = 0; h < kPPL; ++h) cur[h] = nx[h];
+      if (r0 + kGroups < nruns) {
+        slot_of(r0 + kGroups + tid / kLPR, nidx, ncnt, nkey);
+#pragma unroll
+        for (int h = 0; h < kPPL; ++h)
+          if (h < ncnt) nx[h].load(p, nidx + h * kLPR);
+      }
+      // the run's cell: the values that always go there (rho^{n+1}) and the
+      // split-set values of the particles whose position is in it, summed in
+      // registers over the lane's particles
+      float X[4 * KA];
+#pragma unroll
+      for (int e = 0; e < 4 * KA; ++e) X[e] = 0.f;
+      LaneSplit<LS::KS> P[kPPL];
+      bool inA[kPPL];
+      uint32_t outA[kPPL];
 #pragma unroll
       for (int h = 0; h < kPPL; ++h) {
-        const uint32_t kk = (uint32_t)__shfl((int)P[h].kh, gbase + first, 64);
-        if (!taken && ((outA[h] >> first) & 1u)) {
-          kB = kk;
-          taken = true;
+        const bool valid = h < cnt;
+        double x = 0.0, y = 0.0, z = zmin;
+        float ux = 0.f, uy = 0.f, uz = 0.f, qw = 0.f;
+        if (valid) {
+          x = cur[h].x;
+          y = cur[h].y;
+          z = cur[h].z;
+          ux = cur[h].ux;
+          uy = cur[h].uy;
+          uz = (float)cur[h].uz;
+          qw = cur[h].w;
+        }
+        const float ginv = 1.f / sqrtf(1.f + ux * ux + uy * uy + uz * uz);
+        const float vx = ux * ginv, vy = uy * ginv, vz = uz * ginv;
+        ShapePos sp;
+        if constexpr (kEdge) {
+          // rho^n at x^n = x^{n+1} - dt v
+          sp = shape_at(x - dt * (double)vx, y - dt * (double)vy, z - dt * (double)vz, zmin, g);
+          RS::values(qw, sp.eith, P[h].v);
+        } else {
+          // rho^{n+1} at x^{n+1}, in the run's cell (particles beyond the
+          // last radial node share the last key column and deposit nothing)
+          const ShapePos s = shape_at(x, y, z, zmin, g);
+          float vr[RS::K];
+          RS::values(valid && s.i0 < g.nr ? qw : 0.f, s.eith, vr);
+          const float rz[4] = {(1.f - s.fz) * (1.f - s.fr), s.fz * (1.f - s.fr), (1.f - s.fz) * s.fr, s.fz * s.fr};
+#pragma unroll
+          for (int k = 0; k < RS::K; ++k)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) X[n * KA + k] = fmaf(rz[n], vr[k], X[n * KA + k]);
+          // J^{n+1/2} at x^{n+1/2} = x^{n+1} - dt v / 2
+          sp = shape_at(x - 0.5 * dt * (double)vx, y - 0.5 * dt * (double)vy, z - 0.5 * dt * (double)vz, zmin, g);
+          JS::values(qw, vx, vy, vz, sp.eith, P[h].v);
+        }
+        P[h].fz = sp.fz;
+        P[h].fr = sp.fr;
+        P[h].key = pos_key(sp, g.nr);
+        inA[h] = !valid || P[h].key == rkey;
+        outA[h] = (uint32_t)(__ballot(!inA[h]) >> gbase) & kGroupMask;
+        const float fa = inA[h] ? 1.f : 0.f;
+        const float wz[4] = {fa * (1.f - sp.fz) * (1.f - sp.fr), fa * sp.fz * (1.f - sp.fr),
+                             fa * (1.f - sp.fz) * sp.fr, fa * sp.fz * sp.fr};
+#pragma unroll
+        for (int k = 0; k < LS::KS; ++k)
+#pragma unroll
+          for (int n = 0; n < 4; ++n) X[n * KA + LS::KR + k] = fmaf(wz[n], P[h].v[k], X[n * KA + LS::KR + k]);
+      }
+      reduce_scatter4(X, q);
+      if (rkey != kInvalidKey) flush_node<TR, H, M, MODE, true>(lds, X, rkey, g, J0, C0, q);
+      // the group's second cell: that of its first particle outside the
+      // run's cell, in lane order, then particle order
+      uint32_t any = 0;
+#pragma unroll
+      for (int h = 0; h < kPPL; ++h) any |= outA[h];
+      const int first = any ? __ffs(any) - 1 : 0;
+      uint32_t kB = kInvalidKey;
+      {
+        bool taken = false;
+#pragma unroll
+        for (int h = 0; h < kPPL; ++h) {
+          const uint32_t kk = (uint32_t)__shfl((int)P[h].key, gbase + first, 64);
+          if (!taken && ((outA[h] >> first) & 1u)) {
+            kB = kk;
+            taken = true;
+          }
         }
       }
-    }
-    bool inB[kPPL];
-    bool anyB = false;
-#pragma unroll
-    for (int h = 0; h < kPPL; ++h) {
-      inB[h] = !inA[h] && P[h].kh == kB;
-      anyB = anyB || inB[h];
-      if (!inA[h] && !inB[h]) {
-        // a third cell in the group: this particle's own atomics
-        Acc<JS::K> R;
-        R.key = P[h].kh;
-        const float fz = P[h].fz, fr = P[h].fr;
-        const float jz[4] = {(1.f - fz) * (1.f - fr), fz * (1.f - fr), (1.f - fz) * fr, fz * fr};
-#pragma unroll
-        for (int k = 0; k < JS::K; ++k)
-#pragma unroll
-          for (int n = 0; n < 4; ++n) R.a[4 * k + n] = jz[n] * P[h].vj[k];
-        acc_flush<TR, H, JS::K, JS>(lds, R, g, J0, C0, [](int k) { return JS::off(k); });
-      }
-    }
-    const uint64_t bmask = __ballot(anyB);
-    if (bmask) {   // uniform over the wavefront
-      float Y[4 * KB];
-#pragma unroll
-      for (int e = 0; e < 4 * KB; ++e) Y[e] = 0.f;
+      bool inB[kPPL];
+      bool anyB = false;
 #pragma unroll
       for (int h = 0; h < kPPL; ++h) {
-        const float fz = P[h].fz, fr = P[h].fr;
-        const float fb = inB[h] ? 1.f : 0.f;
-        const float jz[4] = {fb * (1.f - fz) * (1.f - fr), fb * fz * (1.f - fr), fb * (1.f - fz) * fr, fb * fz * fr};
+        inB[h] = !inA[h] && P[h].key == kB;
+        anyB = anyB || inB[h];
+        if (!inA[h] && !inB[h]) {
+          // a third cell in the group: this particle's own atomics
+          Acc<LS::KS> R;
+          R.key = P[h].key;
+          const float fz = P[h].fz, fr = P[h].fr;
+          const float wz[4] = {(1.f - fz) * (1.f - fr), fz * (1.f - fr), (1.f - fz) * fr, fz * fr};
 #pragma unroll
-        for (int k = 0; k < JS::K; ++k)
+          for (int k = 0; k < LS::KS; ++k)
 #pragma unroll
-          for (int n = 0; n < 4; ++n) Y[n * KB + k] = fmaf(jz[n], P[h].vj[k], Y[n * KB + k]);
+            for (int n = 0; n < 4; ++n) R.a[4 * k + n] = wz[n] * P[h].v[k];
+          if constexpr (kEdge)
+            acc_flush<TR, H, LS::KS, RS>(lds, R, g, J0, C0, [](int k) { return RS::off(3, k); });
+          else
+            acc_flush<TR, H, LS::KS, JS>(lds, R, g, J0, C0, [](int k) { return JS::off(k); });
+        }
       }
-      reduce_scatter4(Y, q);
-      if ((bmask >> gbase) & kGroupMask) flush_node<TR, H, M, false>(lds, Y, kB, g, J0, C0, q);
+      const uint64_t bmask = __ballot(anyB);
+      if (bmask) {   // uniform over the wavefront
+        float Y[4 * KB];
+#pragma unroll
+        for (int e = 0; e < 4 * KB; ++e) Y[e] = 0.f;
+#pragma unroll
+        for (int h = 0; h < kPPL; ++h) {
+          const float fz = P[h].fz, fr = P[h].fr;
+          const float fb = inB[h] ? 1.f : 0.f;
+          const float wz[4] = {fb * (1.f - fz) * (1.f - fr), fb * fz * (1.f - fr), fb * (1.f - fz) * fr, fb * fz * fr};
+#pragma unroll
+          for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) Y[n * KB + k] = fmaf(wz[n], P[h].v[k], Y[n * KB + k]);
+        }
+        reduce_scatter4(Y, q);
+        if ((bmask >> gbase) & kGroupMask) flush_node<TR, H, M, MODE, false>(lds, Y, kB, g, J0, C0, q);
+      }
     }
-  }
+  }   // pieces
   __syncthreads();
   constexpr int nr_vals = RhoVals<M>::N;
   if (ionblk && chunk == 0) {
-    // the tile's background, once per tile, in FP64, into rho^{n+1}
+    // the tile's background, once per tile, in FP64, into the density this
+    // launch deposits
     const double* src = ionblk + (size_t)t * nr_vals * B::NODES;
-    for (int e = tid; e < nr_vals * B::NODES; e += blockDim.x) {
+    for (int e = tid; e < nr_vals * B::NODES; e += NT) {
       const int k = e / B::NODES, node = e % B::NODES;
-      lds[RS::off(4, k) + node] += src[e];
+      lds[RS::off(kEdge ? 3 : 4, k) + node] += src[e];
     }
     __syncthreads();
   }
+  if (kEdge) {
+    // only the rho^n part of the tile's first slot (the rest is the carry launch's)
+    float* dst = scratch + (size_t)chunk_start[t] * nacc;
+    for (int e = tid; e < nr_vals * B::NODES; e += NT) {
+      const int k = e / B::NODES, node = e % B::NODES;
+      dst[RS::off(3, k) + node] = (float)lds[RS::off(3, k) + node];
+    }
+    return;
+  }
   float* dst = scratch + (size_t)b * nacc;
-  for (int e = tid; e < nacc; e += blockDim.x) dst[e] = (float)lds[e];
+  for (int e = tid; e < nacc; e += NT) dst[e] = (float)lds[e];
 }
 
 // Set-up of the background blocks: the FP64 rho slots of a tile's work items
@@ -1388,18 +1451,23 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
       if constexpr (SHAPE == 1 && M <= 2) {
         static bool attr_lanes = false;
         if (!attr_lanes) {
-          if (!set_lds_limit(k_deposit_lanes<TR, H, M>, lds)) return;
+          if (!set_lds_limit(k_deposit_lanes<TR, H, M, kDepCarry, 256>, lds) ||
+              !set_lds_limit(k_deposit_lanes<TR, H, M, kDepEdgeRho, 1024>, lds))
+            return;
           attr_lanes = true;
         }
-        hipLaunchKernelGGL((k_deposit_lanes<TR, H, M>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
-                           chunk_start, (float*)scratch, ionblk, g, tg, st);
+        hipLaunchKernelGGL((k_deposit_lanes<TR, H, M, kDepCarry, 256>), dim3(d.max_items), dim3(256), lds, s, p, offset,
+                           nchunk, chunk_start, (float*)scratch, ionblk, g, tg, st);
+        if (rho_mode == kRhoCarryShift)
+          hipLaunchKernelGGL((k_deposit_lanes<TR, H, M, kDepEdgeRho, 1024>), dim3(2 * d.ntr), dim3(1024), lds, s, p,
+                             offset, nchunk, chunk_start, (float*)scratch, ionblk, g, tg, st);
       } else {
         hipLaunchKernelGGL((k_deposit<TR, H, M, kDepCarry, SHAPE>), dim3(d.max_items), dim3(256), lds, s, p, offset,
                            nchunk, chunk_start, (float*)scratch, ionblk, g, tg, st);
+        if (rho_mode == kRhoCarryShift)
+          hipLaunchKernelGGL((k_deposit<TR, H, M, kDepEdgeRho, SHAPE>), dim3(2 * d.ntr), dim3(256), lds, s, p, offset,
+                             nchunk, chunk_start, (float*)scratch, ionblk, g, tg, st);
       }
-      if (rho_mode == kRhoCarryShift)
-        hipLaunchKernelGGL((k_deposit<TR, H, M, kDepEdgeRho, SHAPE>), dim3(2 * d.ntr), dim3(256), lds, s, p, offset, nchunk,
-                           chunk_start, (float*)scratch, ionblk, g, tg, st);
     }
   }
   if (stages & kDepCombine) {
