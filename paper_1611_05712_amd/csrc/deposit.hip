@@ -808,8 +808,8 @@ __global__ __launch_bounds__(256) void k_deposit(Parts p, const int* __restrict_
 // shapes: four lanes per run of at most kRun particles of one cell, lane q
 // taking particles q and q + 4 of it.  The runs of a round are consecutive in
 // memory, so a wavefront's loads stay within a few lines.  A lane sums its
-// particles' node contributions in registers, node-major (entry n K + k: value
-// k at node n of the cell), and the four lanes then sum over the group by a
+// particles' node contributions in registers, node-major (slot s of K values:
+// node s ^ q of the cell), and the four lanes then sum over the group by a
 // reduce-scatter (two exchange steps, each halving what a lane keeps), after
 // which lane q holds every value of node q and issues their FP64 LDS atomics
 // at offsets known at compile time.
@@ -827,27 +827,36 @@ __device__ __forceinline__ float dpp_mov(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
 
-// one exchange step over the first N entries: a lane keeps the upper half when
-// `up`, else the lower one, and adds the partner's copy of the half it keeps
-// (the partner keeps the other half)
+// one exchange step over the first N entries: the lane keeps the lower half
+// and adds the partner's upper half to it
 template <int N, int CTRL, int CAP>
-__device__ __forceinline__ void rs_step(float (&a)[CAP], bool up) {
+__device__ __forceinline__ void rs_step(float (&a)[CAP]) {
 #pragma unroll
-  for (int i = 0; i < N / 2; ++i) {
-    const float lo = a[i], hi = a[N / 2 + i];
-    const float send = up ? lo : hi;
-    const float keep = up ? hi : lo;
-    a[i] = keep + dpp_mov<CTRL>(send);
-  }
+  for (int i = 0; i < N / 2; ++i) a[i] += dpp_mov<CTRL>(a[N / 2 + i]);
 }
 
-// sum over the four lanes of a group; afterwards lane q holds the sums of
-// entries q*N/4 .. (q+1)*N/4 - 1 in a[0 .. N/4)
+// Sum over the four lanes of a group of node-major entries (four nodes of K
+// values) that lane q keeps in slots rotated by q: slot s holds node s ^ q.
+// Step one (partner q ^ 2): slots 0, 1 of lane q and slots 2, 3 of its
+// partner hold the same two nodes, q and q ^ 1; step two (partner q ^ 1): slot
+// 0 of lane q and slot 1 of its partner hold node q.  No step depends on the
+// lane, and lane q ends with the sums of node q in a[0 .. K).
 template <int N>
-__device__ __forceinline__ void reduce_scatter4(float (&a)[N], int q) {
-  static_assert(N % 4 == 0 && kLPR == 4, "four lanes per run, whole nodes per lane");
-  rs_step<N, 0x4E>(a, (q & 2) != 0);       // partner q ^ 2: nodes 0, 1 or 2, 3
-  rs_step<N / 2, 0xB1>(a, (q & 1) != 0);   // partner q ^ 1: node q
+__device__ __forceinline__ void reduce_scatter4(float (&a)[N]) {
+  static_assert(N % 4 == 0 && kLPR == 4, "four lanes per run, one node per lane");
+  rs_step<N, 0x4E>(a);       // partner q ^ 2
+  rs_step<N / 2, 0xB1>(a);   // partner q ^ 1
+}
+
+// the four node weights of a position in lane q's rotated slots: slot s gets
+// the weight of node s ^ q (bit 0 of a node: z + 1, bit 1: the outer radial node)
+__device__ __forceinline__ void rotated_weights(float fz, float fr, int q, float scale, float (&w)[4]) {
+  const float z0 = (q & 1) ? fz : 1.f - fz, z1 = (q & 1) ? 1.f - fz : fz;
+  const float r0 = (q & 2) ? fr : 1.f - fr, r1 = (q & 2) ? 1.f - fr : fr;
+  w[0] = scale * z0 * r0;
+  w[1] = scale * z1 * r0;
+  w[2] = scale * z0 * r1;
+  w[3] = scale * z1 * r1;
 }
 
 // The position kinds of the lane-group kernel.  kDepCarry: rho^{n+1} at
@@ -1112,7 +1121,8 @@ __global__ __launch_bounds__(NT) void k_deposit_lanes(Parts p, const int* __rest
           const ShapePos s = shape_at(x, y, z, zmin, g);
           float vr[RS::K];
           RS::values(valid && s.i0 < g.nr ? qw : 0.f, s.eith, vr);
-          const float rz[4] = {(1.f - s.fz) * (1.f - s.fr), s.fz * (1.f - s.fr), (1.f - s.fz) * s.fr, s.fz * s.fr};
+          float rz[4];
+          rotated_weights(s.fz, s.fr, q, 1.f, rz);
 #pragma unroll
           for (int k = 0; k < RS::K; ++k)
 #pragma unroll
@@ -1126,15 +1136,14 @@ __global__ __launch_bounds__(NT) void k_deposit_lanes(Parts p, const int* __rest
         P[h].key = pos_key(sp, g.nr);
         inA[h] = !valid || P[h].key == rkey;
         outA[h] = (uint32_t)(__ballot(!inA[h]) >> gbase) & kGroupMask;
-        const float fa = inA[h] ? 1.f : 0.f;
-        const float wz[4] = {fa * (1.f - sp.fz) * (1.f - sp.fr), fa * sp.fz * (1.f - sp.fr),
-                             fa * (1.f - sp.fz) * sp.fr, fa * sp.fz * sp.fr};
+        float wz[4];
+        rotated_weights(sp.fz, sp.fr, q, inA[h] ? 1.f : 0.f, wz);
 #pragma unroll
         for (int k = 0; k < LS::KS; ++k)
 #pragma unroll
           for (int n = 0; n < 4; ++n) X[n * KA + LS::KR + k] = fmaf(wz[n], P[h].v[k], X[n * KA + LS::KR + k]);
       }
-      reduce_scatter4(X, q);
+      reduce_scatter4(X);
       if (rkey != kInvalidKey) flush_node<TR, H, M, MODE, true>(lds, X, rkey, g, J0, C0, q);
       // the group's second cell: that of its first particle outside the
       // run's cell, in lane order, then particle order
@@ -1183,15 +1192,14 @@ __global__ __launch_bounds__(NT) void k_deposit_lanes(Parts p, const int* __rest
         for (int e = 0; e < 4 * KB; ++e) Y[e] = 0.f;
 #pragma unroll
         for (int h = 0; h < kPPL; ++h) {
-          const float fz = P[h].fz, fr = P[h].fr;
-          const float fb = inB[h] ? 1.f : 0.f;
-          const float wz[4] = {fb * (1.f - fz) * (1.f - fr), fb * fz * (1.f - fr), fb * (1.f - fz) * fr, fb * fz * fr};
+          float wz[4];
+          rotated_weights(P[h].fz, P[h].fr, q, inB[h] ? 1.f : 0.f, wz);
 #pragma unroll
           for (int k = 0; k < KB; ++k)
 #pragma unroll
             for (int n = 0; n < 4; ++n) Y[n * KB + k] = fmaf(wz[n], P[h].v[k], Y[n * KB + k]);
         }
-        reduce_scatter4(Y, q);
+        reduce_scatter4(Y);
         if ((bmask >> gbase) & kGroupMask) flush_node<TR, H, M, MODE, false>(lds, Y, kB, g, J0, C0, q);
       }
     }
