@@ -1456,7 +1456,7 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
       hipLaunchKernelGGL((k_deposit<TR, H, M, kDepFull, SHAPE>), dim3(d.max_items), dim3(256), lds, s, p, offset, nchunk,
                          chunk_start, (float*)scratch, ionblk, g, tg, st);
     } else {
-      if constexpr (SHAPE == 1 && M <= 2) {
+      if constexpr (SHAPE == 1 && M <= 4) {
         static bool attr_lanes = false;
         if (!attr_lanes) {
           if (!set_lds_limit(k_deposit_lanes<TR, H, M, kDepCarry, 256>, lds) ||

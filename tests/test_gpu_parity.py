@@ -670,6 +670,57 @@ def test_c1_deposit_in_the_wake():
             assert np.abs(got - ref).max() < 2e-6 * scale, (m, name, np.abs(got - ref).max() / scale)
 
 
+@pytest.mark.parametrize("modes", [1, 2, 3, 4])
+def test_steady_state_deposit_every_mode_count(modes):
+    """The steady-state deposit (J and rho^{n+1} with rho^n carried over from
+    the previous step and re-deposited in the window-end tile rows) for one to
+    four modes: the small workload with the moving window, six steps, then one
+    gather + push and one deposit on the GPU; the oracle deposits the GPU's own
+    pushed particles with the ion lattice moved into the current window.
+    Every source of every mode node by node, away from the three columns at
+    each end of the window (as in the full-size wake test)."""
+    import dataclasses
+    wl = dataclasses.replace(preset("small"), n_modes=modes)
+    sim = _sim(wl)
+    sim.step(6)
+    zmin, _ = sim.state()
+    sim.gather_push()
+    names = [s.name for s in wl.species if s.mobile]
+    after = {n: sim.get_particles(n) for n in names}
+    sim.deposit()
+    species = []
+    for s in wl.species:
+        if s.mobile:
+            a = after[s.name]
+            species.append(Species(s.name, s.q, s.m, True, a["x"], a["y"], a["z"],
+                                   a["ux"].astype(np.float32), a["uy"].astype(np.float32), a["uz"],
+                                   a["w"].astype(np.float32), diag=True))
+        else:   # the lattice of the initial window, moved with the window
+            species.append(Species(s.name, s.q, s.m, False, s.x, s.y, s.z + (zmin - wl.zmin), s.ux, s.uy,
+                                   s.uz, s.w))
+    ow = Workload("small-deposit", wl.nz, wl.nr, modes, wl.order, wl.dz, wl.dr, wl.dt, zmin, False,
+                  wl.kperp_grid, 1, species)
+    o = OracleSim(ow)
+    for sp in o.species:
+        if sp.mobile:
+            ginv = 1.0 / np.sqrt(1.0 + sp.ux.astype(np.float64) ** 2 + sp.uy.astype(np.float64) ** 2
+                                 + sp.uz.astype(np.float64) ** 2)
+            sp.vx, sp.vy, sp.vz = sp.ux * ginv, sp.uy * ginv, sp.uz * ginv
+            sp.xn = (sp.x - wl.dt * sp.vx, sp.y - wl.dt * sp.vy, sp.z - wl.dt * sp.vz)
+        else:
+            sp.xn = (sp.x, sp.y, sp.z)
+    o.deposit()
+    want = {"J+": o.J[:, 0], "J-": o.J[:, 1], "Jz": o.J[:, 2], "rho_old": o.rho_old,
+            "rho_new": o.rho_new}
+    inner = slice(3, wl.nz - 3)
+    for m in range(modes):
+        for name, w in want.items():
+            got = sim.get_field(m, name)[:, inner]
+            ref = w[m][:, inner]
+            scale = max(np.abs(ref).max(), 1e-30)
+            assert np.abs(got - ref).max() < 2e-6 * scale, (m, name, np.abs(got - ref).max() / scale)
+
+
 def test_c0_fifty_steps_against_stored_oracle_run():
     """The same workload for 50 steps: drive moments after 1, 10, 25 and 50
     steps within relative 1e-4, field norms within 1e-4, live particle count
