@@ -197,7 +197,8 @@ int pic_init(const pic_config* cfg, const pic_species* species, int n_species,
 /* Step order: gather_push -> deposit -> spectral_push, repeated.  Any other
  * order returns PIC_ESTATE.  Particle storage order changes at every deposit. */
 
-/* Gathers E^n, B^n at x^n (linear shapes, 4 nodes per mode), Boris-pushes
+/* Gathers E^n, B^n at x^n (linear shapes, 4 nodes per mode; 16 with
+ * shape_order = 3), Boris-pushes
  * u^{n-1/2} -> u^{n+1/2} and moves x^{n+1} = x^n + dt u^{n+1/2}/gamma.
  * Fields live at integer steps and momenta at half steps, the staggering the
  * PSATD update (1a)-(1b) assumes when it takes J at n+1/2 and rho at n, n+1
@@ -209,8 +210,8 @@ int pic_gather_push(pic_ctx* ctx);
 /* Sorts the particles by cell, then deposits rho^n at x^n, J^{n+1/2} at
  * x^{n+1/2} = x^{n+1} - dt v^{n+1/2}/2 with v^{n+1/2} and rho^{n+1} at x^{n+1}:
  * the three source time levels of the E update (1a) and of the current
- * correction (Sec. "Finite order pseudo-spectral solvers").  Linear shapes;
- * mode m of a density carries exp(i m theta_p) and is divided by the ring
+ * correction (Sec. "Finite order pseudo-spectral solvers").  Linear shapes
+ * (cubic B-splines with shape_order = 3); mode m of a density carries exp(i m theta_p) and is divided by the ring
  * volume 2 pi r_i dr dz; below the first radial node the inner shape node is
  * the ghost node -dr/2, folded onto node 0 with the sign (-1)^nu of the
  * component's Hankel order.  The immobile background density is added node by
