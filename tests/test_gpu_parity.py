@@ -670,18 +670,27 @@ def test_c1_deposit_in_the_wake():
             assert np.abs(got - ref).max() < 2e-6 * scale, (m, name, np.abs(got - ref).max() / scale)
 
 
-@pytest.mark.parametrize("modes", [1, 2, 3, 4])
-def test_steady_state_deposit_every_mode_count(modes):
+@pytest.mark.parametrize("modes,dense", [(1, False), (2, False), (3, False), (4, False), (2, True)])
+def test_steady_state_deposit_every_mode_count(modes, dense):
     """The steady-state deposit (J and rho^{n+1} with rho^n carried over from
     the previous step and re-deposited in the window-end tile rows) for one to
     four modes: the small workload with the moving window, six steps, then one
     gather + push and one deposit on the GPU; the oracle deposits the GPU's own
     pushed particles with the ion lattice moved into the current window.
     Every source of every mode node by node, away from the three columns at
-    each end of the window (as in the full-size wake test)."""
+    each end of the window (as in the full-size wake test).  The dense case
+    adds a 40,000-particle core about one cell wide and takes 2048-particle
+    chunks, so its tiles are cut into several work items whose slots the chunk
+    reduction sums."""
     import dataclasses
+    from workloads import _bunch_species
     wl = dataclasses.replace(preset("small"), n_modes=modes)
+    if dense:
+        core = _bunch_species("core", 40000, 20e-12, 200.0, 0.04, 0.04, 0.45 * wl.nz * wl.dz, 5, True)
+        wl = dataclasses.replace(wl, species=list(wl.species) + [core])
     sim = _sim(wl)
+    if dense:
+        sim.set_tuning(0, 2048)
     sim.step(6)
     zmin, _ = sim.state()
     sim.gather_push()
