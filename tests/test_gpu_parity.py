@@ -722,12 +722,19 @@ def test_steady_state_deposit_every_mode_count(modes, dense):
     want = {"J+": o.J[:, 0], "J-": o.J[:, 1], "Jz": o.J[:, 2], "rho_old": o.rho_old,
             "rho_new": o.rho_new}
     inner = slice(3, wl.nz - 3)
+    # The dense tile's ~22 chunks each round their FP64 block to an FP32 slot
+    # and the slots are summed in FP32.  For the azimuthal modes of the core
+    # (contributions at random angles, so a chunk's partial sum is several
+    # times the tile's total) those roundings reach a few 2^-24 x 22 of the
+    # total: 2.0e-6 of the plane's maximum was seen for J+ of mode 1, hence
+    # 1e-5 there; unchunked tiles round once, 2e-6.
+    tol = 1e-5 if dense else 2e-6
     for m in range(modes):
         for name, w in want.items():
             got = sim.get_field(m, name)[:, inner]
             ref = w[m][:, inner]
             scale = max(np.abs(ref).max(), 1e-30)
-            assert np.abs(got - ref).max() < 2e-6 * scale, (m, name, np.abs(got - ref).max() / scale)
+            assert np.abs(got - ref).max() < tol * scale, (m, name, np.abs(got - ref).max() / scale)
 
 
 def test_c0_fifty_steps_against_stored_oracle_run():
