@@ -914,87 +914,32 @@ struct LaneSplit {
   float v[K];
 };
 
-// kDepCarry: one workgroup per work item (NT = 256), the slot written whole.
-// kDepEdgeRho: one workgroup per tile of the two tile rows at the window ends
-// (all of its particles, in pieces of one chunk), rho^n written into the rho^n
-// part of the tile's first slot.
+// One pass of the lane-group deposit over the particles of a tile.
+// kDepCarry: J^{n+1/2} and rho^{n+1} of the work item's particles [f0, f1);
+// kDepEdgeRho: rho^n of all the tile's particles, in pieces of one chunk.
+// Sums into the FP64 block `lds`; the tile's row table is already in LDS.
 template <int TR, int H, int M, int MODE, int NT>
-__global__ __launch_bounds__(NT) void k_deposit_lanes(Parts p, const int* __restrict__ offset,
-                                                      const int* __restrict__ nchunk,
-                                                      const int* __restrict__ chunk_start,
-                                                      float* __restrict__ scratch, const double* __restrict__ ionblk,
-                                                      Grid g, TileGeom tg, DevState* st) {
+__device__ __forceinline__ void lane_pass(const Parts& p, const int* __restrict__ offset, const Grid& g,
+                                          const TileGeom& tg, double* __restrict__ lds, const int* rowstart,
+                                          const int* rowpref, uint16_t* runpref, int* cfirst, int* ccount,
+                                          int* wsum, int J0, int C0, int C1, int f0, int f1, int total,
+                                          double zmin) {
   using B = Blk<TR, H>;
   using RS = RhoSet<M, B::NODES>;
   using JS = JSet<M, B::NODES>;
   using LS = LaneSets<M, B::NODES, MODE>;
   static_assert(MODE == kDepCarry || MODE == kDepEdgeRho, "steady-state modes");
   constexpr bool kEdge = LS::kEdge;
-  extern __shared__ double lds[];
-  constexpr int nacc = Vals<M>::N * B::NODES;
   constexpr int kCells = kTZ * TR;
-  constexpr int kWaves = NT / 64;
   constexpr int kGroups = NT / kLPR;          // runs per round
   constexpr int KA = LS::KR + LS::KS;         // values per node, run cell
   constexpr int KB = LS::KS;                  // values per node, second cell
   constexpr uint32_t kGroupMask = (1u << kLPR) - 1u;
-  __shared__ int rowstart[kTZ];
-  __shared__ int rowpref[kTZ + 1];
-  __shared__ uint16_t runpref[kCells + 1];
-  __shared__ int cfirst[kCells];   // sorted index of each cell's first particle (clipped to the piece)
-  __shared__ int ccount[kCells];   // its particles in the piece
-  __shared__ int wsum[kWaves];
-  __shared__ int s_tile;
-  const int b = blockIdx.x;
   const int tid = threadIdx.x;
-  if (kEdge) {
-    // edge tiles: tz = 0 and tz = ntz - 1 of every radial tile column
-    if (tid == 0) s_tile = (b >> 1) * tg.ntz + ((b & 1) ? tg.ntz - 1 : 0);
-  } else {
-    if (b == 0 && tid == 0) {
-      st->n_part = st->n_live;
-      if (chunk_start[tg.ntiles] > (int)gridDim.x) st->overflow = 2;   // work list larger than the launch
-    }
-    if (b >= chunk_start[tg.ntiles]) return;   // uniform per workgroup
-    if (tid == 0) {
-      int lo = 0, hi = tg.ntiles;   // chunk_start[lo] <= b < chunk_start[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (chunk_start[mid] <= b) lo = mid;
-        else hi = mid;
-      }
-      s_tile = lo;
-    }
-  }
-  for (int e = tid; e < nacc; e += NT) lds[e] = 0.0;
-  __syncthreads();
-  const int t = s_tile;
-  const int chunk = kEdge ? 0 : b - chunk_start[t];
-  const int J0 = (t % tg.ntz) * kTZ, C0 = (t / tg.ntz) * TR;
-  const int C1 = min(C0 + TR, g.ncol);
-  if (tid < kTZ) {
-    const int j = J0 + tid;
-    const int a = offset[j * g.ncol + C0];
-    rowstart[tid] = a;
-    rowpref[tid + 1] = offset[j * g.ncol + C1] - a;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    rowpref[0] = 0;
-    for (int r = 1; r <= kTZ; ++r) rowpref[r] += rowpref[r - 1];
-  }
-  __syncthreads();
-  const int total = rowpref[kTZ];
-  const double zmin = st->zmin;
   const double dt = g.dt;
-  const int npiece = kEdge ? max(1, (total + tg.chunk - 1) / tg.chunk) : 1;
-  int f0 = 0, f1 = total;
-  if (!kEdge && nchunk[t] != 1) {
-    f0 = chunk * tg.chunk;
-    f1 = min(total, f0 + tg.chunk);
-  }
   const int q = tid & (kLPR - 1);
   const int lane = tid & 63, gbase = lane & ~(kLPR - 1);
+  const int npiece = kEdge ? max(1, (total + tg.chunk - 1) / tg.chunk) : 1;
   for (int piece = 0; piece < npiece; ++piece) {
     if (kEdge) {
       f0 = piece * tg.chunk;
@@ -1204,28 +1149,124 @@ __global__ __launch_bounds__(NT) void k_deposit_lanes(Parts p, const int* __rest
       }
     }
   }   // pieces
+}
+
+// The steady-state deposit, one workgroup per work item (NT threads): the
+// pass of kDepCarry over the item's particles, written as the item's whole
+// slot.  With `edge_rows` (the window moved), the first work item of each tile
+// of the two tile rows at the window ends also takes the kDepEdgeRho pass over
+// all of its tile's particles (rho^n where particles left and the new column
+// entered); those items get the first workgroups of the launch, so that their
+// longer work overlaps the others instead of ending the launch.
+template <int TR, int H, int M, int NT>
+__global__ __launch_bounds__(NT) void k_deposit_lanes(Parts p, const int* __restrict__ offset,
+                                                      const int* __restrict__ nchunk,
+                                                      const int* __restrict__ chunk_start,
+                                                      float* __restrict__ scratch, const double* __restrict__ ionblk,
+                                                      Grid g, TileGeom tg, DevState* st, int edge_rows) {
+  using B = Blk<TR, H>;
+  using RS = RhoSet<M, B::NODES>;
+  extern __shared__ double lds[];
+  constexpr int nacc = Vals<M>::N * B::NODES;
+  constexpr int kCells = kTZ * TR;
+  constexpr int kWaves = NT / 64;
+  __shared__ int rowstart[kTZ];
+  __shared__ int rowpref[kTZ + 1];
+  __shared__ uint16_t runpref[kCells + 1];
+  __shared__ int cfirst[kCells];   // sorted index of each cell's first particle (clipped to the piece)
+  __shared__ int ccount[kCells];   // its particles in the piece
+  __shared__ int wsum[kWaves];
+  __shared__ int s_tile, s_item, s_edge;
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (b == 0 && tid == 0) {
+    st->n_part = st->n_live;
+    if (chunk_start[tg.ntiles] > (int)gridDim.x) st->overflow = 2;   // work list larger than the launch
+  }
+  const int items = chunk_start[tg.ntiles];
+  if (b >= items) return;   // uniform per workgroup
+  if (tid == 0) {
+    // edge tiles in ascending order: tz = 0 and tz = ntz - 1 of every radial
+    // tile column (one tile per column when ntz = 1)
+    const int per_col = tg.ntz > 1 ? 2 : 1;
+    const int n_edge = edge_rows ? per_col * tg.ntr : 0;
+    auto edge_tile = [&](int e) { return (e / per_col) * tg.ntz + ((e % per_col) ? tg.ntz - 1 : 0); };
+    int item, edge = 0;
+    if (b < n_edge) {
+      item = chunk_start[edge_tile(b)];
+      edge = 1;
+    } else {
+      // the (b - n_edge)-th item that is not an edge tile's first: skip the k
+      // edge items E_j with E_j - j <= b - n_edge (E_j - j ascends with j)
+      const int pos = b - n_edge;
+      int lo = 0, hi = n_edge;   // count of j with E_j - j <= pos
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (chunk_start[edge_tile(mid)] - mid <= pos) lo = mid + 1;
+        else hi = mid;
+      }
+      item = pos + lo;
+    }
+    int lo = 0, hi = tg.ntiles;   // chunk_start[lo] <= item < chunk_start[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (chunk_start[mid] <= item) lo = mid;
+      else hi = mid;
+    }
+    s_tile = lo;
+    s_item = item;
+    s_edge = edge;
+  }
+  __syncthreads();
+  const int item = s_item;
+  // a work list larger than the launch (flagged above) has items without a
+  // slot: those are left out rather than written past the scratch slots
+  if (item >= (int)gridDim.x) return;   // uniform per workgroup
+  for (int e = tid; e < nacc; e += NT) lds[e] = 0.0;
+  __syncthreads();
+  const int t = s_tile;
+  const bool edge = s_edge != 0;
+  const int chunk = item - chunk_start[t];
+  const int J0 = (t % tg.ntz) * kTZ, C0 = (t / tg.ntz) * TR;
+  const int C1 = min(C0 + TR, g.ncol);
+  if (tid < kTZ) {
+    const int j = J0 + tid;
+    const int a = offset[j * g.ncol + C0];
+    rowstart[tid] = a;
+    rowpref[tid + 1] = offset[j * g.ncol + C1] - a;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    rowpref[0] = 0;
+    for (int r = 1; r <= kTZ; ++r) rowpref[r] += rowpref[r - 1];
+  }
+  __syncthreads();
+  const int total = rowpref[kTZ];
+  const double zmin = st->zmin;
+  int f0 = 0, f1 = total;
+  if (nchunk[t] != 1) {
+    f0 = chunk * tg.chunk;
+    f1 = min(total, f0 + tg.chunk);
+  }
+  lane_pass<TR, H, M, kDepCarry, NT>(p, offset, g, tg, lds, rowstart, rowpref, runpref, cfirst, ccount, wsum, J0,
+                                     C0, C1, f0, f1, total, zmin);
+  if (edge)   // uniform per workgroup
+    lane_pass<TR, H, M, kDepEdgeRho, NT>(p, offset, g, tg, lds, rowstart, rowpref, runpref, cfirst, ccount, wsum,
+                                         J0, C0, C1, 0, total, total, zmin);
   __syncthreads();
   constexpr int nr_vals = RhoVals<M>::N;
   if (ionblk && chunk == 0) {
-    // the tile's background, once per tile, in FP64, into the density this
-    // launch deposits
+    // the tile's background, once per tile, in FP64, into rho^{n+1} (and into
+    // rho^n where this item deposits it)
     const double* src = ionblk + (size_t)t * nr_vals * B::NODES;
     for (int e = tid; e < nr_vals * B::NODES; e += NT) {
       const int k = e / B::NODES, node = e % B::NODES;
-      lds[RS::off(kEdge ? 3 : 4, k) + node] += src[e];
+      lds[RS::off(4, k) + node] += src[e];
+      if (edge) lds[RS::off(3, k) + node] += src[e];
     }
     __syncthreads();
   }
-  if (kEdge) {
-    // only the rho^n part of the tile's first slot (the rest is the carry launch's)
-    float* dst = scratch + (size_t)chunk_start[t] * nacc;
-    for (int e = tid; e < nr_vals * B::NODES; e += NT) {
-      const int k = e / B::NODES, node = e % B::NODES;
-      dst[RS::off(3, k) + node] = (float)lds[RS::off(3, k) + node];
-    }
-    return;
-  }
-  float* dst = scratch + (size_t)b * nacc;
+  float* dst = scratch + (size_t)item * nacc;
   for (int e = tid; e < nacc; e += NT) dst[e] = (float)lds[e];
 }
 
@@ -1459,16 +1500,12 @@ static void launch_dep(const Parts& p, const int* offset, int* nchunk, int* chun
       if constexpr (SHAPE == 1 && M <= 4) {
         static bool attr_lanes = false;
         if (!attr_lanes) {
-          if (!set_lds_limit(k_deposit_lanes<TR, H, M, kDepCarry, 256>, lds) ||
-              !set_lds_limit(k_deposit_lanes<TR, H, M, kDepEdgeRho, 1024>, lds))
-            return;
+          if (!set_lds_limit(k_deposit_lanes<TR, H, M, 256>, lds)) return;
           attr_lanes = true;
         }
-        hipLaunchKernelGGL((k_deposit_lanes<TR, H, M, kDepCarry, 256>), dim3(d.max_items), dim3(256), lds, s, p, offset,
-                           nchunk, chunk_start, (float*)scratch, ionblk, g, tg, st);
-        if (rho_mode == kRhoCarryShift)
-          hipLaunchKernelGGL((k_deposit_lanes<TR, H, M, kDepEdgeRho, 1024>), dim3(2 * d.ntr), dim3(1024), lds, s, p,
-                             offset, nchunk, chunk_start, (float*)scratch, ionblk, g, tg, st);
+        hipLaunchKernelGGL((k_deposit_lanes<TR, H, M, 256>), dim3(d.max_items), dim3(256), lds, s, p, offset,
+                           nchunk, chunk_start, (float*)scratch, ionblk, g, tg, st,
+                           rho_mode == kRhoCarryShift ? 1 : 0);
       } else {
         hipLaunchKernelGGL((k_deposit<TR, H, M, kDepCarry, SHAPE>), dim3(d.max_items), dim3(256), lds, s, p, offset,
                            nchunk, chunk_start, (float*)scratch, ionblk, g, tg, st);
