@@ -86,7 +86,8 @@ def _phase_units(name, wl, n_part, prec):
 
 # sources each measured kernel is built from: its traffic record stays valid
 # while these files are unchanged
-KERNEL_SOURCES = {"deposit": ("deposit.hip", "common.h", "launch.h")}
+KERNEL_SOURCES = {"deposit": ("deposit.hip", "common.h", "launch.h"),
+                  "sort": ("particles.hip", "common.h", "launch.h")}
 
 
 def _kernel_sources_hash(kernel="deposit"):
